@@ -1,0 +1,194 @@
+/*
+ * reap_spgemm.h -- sparse general matrix-matrix product C = A * B on CSR
+ * operands, computed on an AMD Instinct MI355X (gfx950) GPU.
+ *
+ * The operation is the paper's row-by-row sparse product (Section III-A,
+ * Algorithm 1): each row i of C is formed from the rows of B selected by the
+ * column indices of row i of A; every matching pair contributes one partial
+ * product a_ik * b_kj, and products with the same column are summed into one
+ * entry.  Rows of C are returned with strictly ascending column indices.
+ * Entries whose products cancel to zero are kept (the algorithm emits every
+ * column of the row's column set).
+ *
+ * The work is split in two calls, as the allocation of C requires:
+ *   symbolic -- counts partial products and the number of entries of every row
+ *               of C, writes C's row pointer, returns nnz(C) to the host;
+ *   numeric  -- fills C's column indices and values.
+ * Memory: every A, B and C array is owned by the caller and lives in device
+ * memory.  The plan owns only its workspace (per-row counts and classes, long
+ * row scratch), which it allocates in `symbolic`, reuses across calls and
+ * releases in `destroy`.
+ *
+ * Errors: every entry point returns a reap_status_t; nothing throws or aborts.
+ * After an error the plan may still be passed to reap_spgemm_destroy.  A plan
+ * is not thread-safe; distinct plans are independent.
+ */
+#ifndef REAP_SPGEMM_H
+#define REAP_SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct reap_spgemm_s* reap_spgemm_t;
+
+typedef enum {
+    REAP_OK = 0,
+    REAP_ERR_INVALID_ARG = 1,    /* null pointer, negative size, A.cols != B.rows, dtype mismatch */
+    REAP_ERR_BAD_CSR = 2,        /* validation found a malformed operand (opt-in check) */
+    REAP_ERR_INDEX_OVERFLOW = 3, /* nnz(C) does not fit the requested C row-pointer type */
+    REAP_ERR_OUT_OF_MEMORY = 4,  /* workspace allocation failed */
+    REAP_ERR_STATE = 5,          /* numeric called without a matching symbolic */
+    REAP_ERR_HIP = 6             /* a HIP runtime call failed (includes earlier kernel faults) */
+} reap_status_t;
+
+typedef enum { REAP_F32 = 0, REAP_F64 = 1 } reap_dtype_t;
+typedef enum { REAP_I32 = 0, REAP_I64 = 1 } reap_index_t;
+
+/*
+ * One CSR operand in device memory (CSR as in the paper's Section I and
+ * Section III-A: row pointer, column index, value).
+ *   rows, cols    -- matrix shape (>= 0);
+ *   nnz           -- number of stored entries; must equal row_ptr[rows];
+ *   row_ptr_type  -- REAP_I32 or REAP_I64: element type of row_ptr;
+ *   row_ptr       -- rows+1 entries, row_ptr[0] = 0, non-decreasing;
+ *   col_idx       -- nnz int32 column indices in [0, cols); any order inside a
+ *                    row; a repeated column adds;
+ *   values        -- nnz values of the plan's dtype (float or double).
+ * Pointers may be NULL only when the corresponding count is zero.
+ */
+typedef struct {
+    int64_t rows, cols, nnz;
+    reap_index_t row_ptr_type;
+    const void* row_ptr;
+    const int32_t* col_idx;
+    const void* values;
+} reap_csr_t;
+
+/*
+ * Tuning and test options.  Zero-initialise and set what you need, or pass
+ * NULL for defaults.  Thresholds only change which kernel handles a row,
+ * never the result.
+ *   validate          -- non-zero: check both operands (row_ptr monotone, ends
+ *                        at nnz, columns in range) before use; costs one pass.
+ *   wave_max_products -- rows with at most this many partial products (and at
+ *                        most 64 entries in A) are computed by one wavefront
+ *                        (<= 1024; 0 = default 1024).
+ *   wave_max_span     -- widest column window (max col - min col + 1) a
+ *                        wavefront handles with a bitmap (<= 32768; 0 = default).
+ *   wave_hash_products-- rows wider than that window but with at most this many
+ *                        products use a wavefront hash table (<= 256; 0 = default).
+ *   group_lds_span    -- widest window a workgroup keeps as a bitmap in LDS
+ *                        (<= 262144; 0 = default); wider rows use device memory.
+ *   group_lds_values  -- most entries a workgroup accumulates in LDS
+ *                        (<= 8192; 0 = default); longer rows accumulate in
+ *                        device memory.
+ *   profile           -- non-zero: record per-phase device times (see
+ *                        reap_spgemm_phase_times).
+ *   wave_small_values -- rows of C with at most this many entries (and a
+ *                        window of at most 20480 columns) use the compact
+ *                        wavefront kernel (<= 128; 0 = default 128).
+ * For every threshold, 0 selects the default and a negative value 0.
+ */
+typedef struct {
+    int32_t validate;
+    int32_t wave_max_products;
+    int32_t wave_max_span;
+    int32_t wave_hash_products;
+    int32_t group_lds_span;
+    int32_t group_lds_values;
+    int32_t profile;
+    int32_t wave_small_values;
+    int32_t reserved[8];
+} reap_options_t;
+
+/* Per-class row counts of the last symbolic pass (how rows were binned). */
+typedef struct {
+    int64_t empty;        /* rows with no partial product */
+    int64_t wave_bitmap;  /* one wavefront, LDS bitmap over the column window */
+    int64_t wave_hash;    /* one wavefront, LDS hash table + sort */
+    int64_t group;        /* one workgroup (long rows), LDS or device bitmap */
+    int64_t max_row_products;
+    int64_t max_row_nnz;
+} reap_bin_stats_t;
+
+/*
+ * Create a plan for products with values of type `dtype` and a C row pointer
+ * of type `c_row_ptr_type`, enqueued on `stream` (a hipStream_t; NULL = the
+ * default stream).  Binds to the current HIP device.  *plan is set to NULL on
+ * failure.  Errors: INVALID_ARG, HIP.
+ */
+reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype,
+                                 reap_index_t c_row_ptr_type, void* stream,
+                                 const reap_options_t* opts);
+
+/*
+ * Symbolic pass (the row product count, the binning of rows by their product
+ * count, the per-row count of distinct columns -- the column set COLB of the
+ * paper's Algorithm 1 -- and the prefix scan that places each row of C).
+ *   c_row_ptr   -- device, A.rows+1 elements of the plan's C row-pointer type;
+ *                  written with the exclusive scan of the row counts.
+ *   c_nnz       -- host, required: receives nnz(C).
+ *   n_products  -- host, optional: receives the number of partial products
+ *                  (sum over i of sum over k in A_i of nnz(B_k)).
+ *   workspace_bytes -- host, optional: device bytes the plan holds.
+ * Blocks until c_nnz is known (the only host synchronisation of the pair).
+ * Errors: INVALID_ARG (shapes, nulls, A.cols != B.rows), BAD_CSR (validate),
+ * INDEX_OVERFLOW (c_row_ptr_type I32 and nnz(C) > INT32_MAX; c_row_ptr is then
+ * unspecified), OUT_OF_MEMORY, HIP.
+ */
+reap_status_t reap_spgemm_symbolic(reap_spgemm_t plan, const reap_csr_t* A, const reap_csr_t* B,
+                                   void* c_row_ptr, int64_t* c_nnz, int64_t* n_products,
+                                   size_t* workspace_bytes);
+
+/*
+ * Numeric pass: multiply, accumulate and write C (Algorithm 1's products,
+ * sort and merge).  A and B must have the same shapes and patterns as in the
+ * preceding symbolic call on this plan (values may differ); c_row_ptr is the
+ * array symbolic wrote.  c_col_idx and c_values are device arrays of nnz(C)
+ * elements.  FP32 operands are multiplied and summed in FP64 and rounded once
+ * on write.  Asynchronous on the plan's stream; a kernel fault surfaces as
+ * REAP_ERR_HIP at a later call or stream synchronisation.
+ * Errors: INVALID_ARG, STATE (no symbolic, or shapes differ from it), HIP.
+ */
+reap_status_t reap_spgemm_numeric(reap_spgemm_t plan, const reap_csr_t* A, const reap_csr_t* B,
+                                  const void* c_row_ptr, int32_t* c_col_idx, void* c_values);
+
+/* Release the plan's workspace and the plan (NULL is accepted). */
+reap_status_t reap_spgemm_destroy(reap_spgemm_t plan);
+
+/* Row classes of the last symbolic pass.  Errors: INVALID_ARG, STATE. */
+reap_status_t reap_spgemm_bin_stats(reap_spgemm_t plan, reap_bin_stats_t* out);
+
+/*
+ * Device milliseconds per call of each phase, averaged over the calls made
+ * since the plan was created or last reset, when the plan was created with
+ * opts->profile set (HIP events recorded on the plan's stream around each
+ * phase; no extra host synchronisation is added to symbolic or numeric).
+ *   out[0] symbolic kernels (row product counts, binning, per-row column
+ *          counts), out[1] scan, out[2] numeric wavefront-bitmap kernels,
+ *   out[3] numeric wavefront-hash kernel, out[4] numeric workgroup kernel,
+ *   out[5] whole numeric call, out[6] 0, out[7] number of numeric calls
+ *   averaged.  A phase that did not run reads 0.
+ *   n = capacity of out (<= 8 is read).
+ * Synchronises the plan's stream.  Errors: INVALID_ARG, STATE (no profile).
+ */
+reap_status_t reap_spgemm_phase_times(reap_spgemm_t plan, float* out, int n);
+
+/* Clears the accumulated phase times.  Errors: INVALID_ARG, STATE (no profile). */
+reap_status_t reap_spgemm_phase_reset(reap_spgemm_t plan);
+
+/* Static description of a status code. */
+const char* reap_status_string(reap_status_t s);
+
+/* Library version, "major.minor.patch". */
+const char* reap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REAP_SPGEMM_H */

@@ -1,0 +1,109 @@
+// Wavefront-level helpers for gfx950 (CDNA4, 64-lane wavefronts).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace reap {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Orders this wavefront's LDS accesses across lanes (no cross-wave effect).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of m in lanes strictly below this lane.
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Inclusive prefix sum across the wavefront.
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long long wave_incl_scan_i64(long long v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        long long u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan over a workgroup of NT threads; returns this thread's
+// exclusive prefix and writes the block total to *total.
+template <int NT>
+__device__ __forceinline__ long long block_excl_scan_i64(long long v, long long* s_red, long long* total) {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const long long incl = wave_incl_scan_i64(v);
+    __syncthreads();
+    if (lane == kWave - 1) s_red[w] = incl;
+    __syncthreads();
+    long long before = 0, all = 0;
+#pragma unroll
+    for (int x = 0; x < NT / kWave; ++x) {
+        const long long t = s_red[x];
+        before += (x < w) ? t : 0;
+        all += t;
+    }
+    *total = all;
+    return before + incl - v;
+}
+
+// Maps hardware workgroup ids (dispatched round-robin over the XCDs) to
+// logical ids so that each XCD processes one contiguous range of logical ids;
+// neighbouring rows then share that XCD's L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_contiguous_block(int b, int n) {
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    const int xcd = b % kNumXcd, idx = b / kNumXcd;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Multiplicative hash for LDS open-addressing tables (Knuth's constant).
+__device__ __forceinline__ uint32_t hash_col(int32_t c) { return (uint32_t)c * 2654435761u; }
+
+}  // namespace reap

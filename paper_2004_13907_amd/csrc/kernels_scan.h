@@ -1,0 +1,122 @@
+// Exclusive prefix scan of the per-row entry counts of C into C's row pointer
+// (the allocation step that the row-by-row product needs before any value is
+// written), plus the reduction of the symbolic pass's statistics.
+#pragma once
+#include "device_utils.h"
+#include "spgemm_common.h"
+
+namespace reap {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // rows per tile
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t* __restrict__ rnnz, int64_t m,
+                                                             long long* __restrict__ tile_sums) {
+    __shared__ long long s_red[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j)
+        if (base + j < m) s += rnnz[base + j];
+    long long total;
+    block_excl_scan_i64<kScanThreads>(s, s_red, &total);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// One workgroup: scans the tile sums in place (exclusive), folds the
+// per-workgroup statistics of the symbolic kernel into the counters, and
+// writes C.row_ptr[m] = nnz(C).
+template <typename IdxC>
+__global__ void __launch_bounds__(1024) k_scan_spine(long long* __restrict__ tile_sums, int ntiles,
+                                                     const WGPart* __restrict__ parts, int nparts,
+                                                     Counters* ctr, IdxC* c_rp, int64_t m) {
+    __shared__ long long s_red[1024 / kWave];
+    __shared__ unsigned long long s_prod[1024 / kWave];
+    __shared__ unsigned int s_cls[1024 / kWave][kNumClasses];
+    __shared__ unsigned int s_max[1024 / kWave][2];
+    long long carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const long long v = (b < ntiles) ? tile_sums[b] : 0;
+        long long total;
+        const long long ex = block_excl_scan_i64<1024>(v, s_red, &total);
+        if (b < ntiles) tile_sums[b] = carry + ex;
+        carry += total;
+    }
+    unsigned long long prod = 0;
+    unsigned int cls[kNumClasses] = {0, 0, 0, 0, 0};
+    unsigned int mp = 0, mn = 0;
+    for (int x = threadIdx.x; x < nparts; x += 1024) {
+        const WGPart& q = parts[x];
+        prod += q.products;
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) cls[c] += q.cls[c];
+        mp = max(mp, q.max_prod);
+        mn = max(mn, q.max_nnz);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        prod += __shfl_xor(prod, o, kWave);
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) cls[c] += __shfl_xor(cls[c], o, kWave);
+        mp = max(mp, __shfl_xor(mp, o, kWave));
+        mn = max(mn, __shfl_xor(mn, o, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        s_prod[w] = prod;
+#pragma unroll
+        for (int c = 0; c < kNumClasses; ++c) s_cls[w][c] = cls[c];
+        s_max[w][0] = mp;
+        s_max[w][1] = mn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int x = 1; x < 1024 / kWave; ++x) {
+            prod += s_prod[x];
+            for (int c = 0; c < kNumClasses; ++c) cls[c] += s_cls[x][c];
+            mp = max(mp, s_max[x][0]);
+            mn = max(mn, s_max[x][1]);
+        }
+        ctr->products += prod;   // the long-row kernel has already added its rows
+        for (int c = 0; c < kNumClasses; ++c) ctr->cls[c] = cls[c];
+        ctr->max_prod = max(ctr->max_prod, mp);
+        ctr->max_nnz = max(ctr->max_nnz, mn);
+        ctr->nnz = (unsigned long long)carry;
+        c_rp[m] = (IdxC)carry;
+    }
+}
+
+template <typename IdxC>
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* __restrict__ rnnz, int64_t m,
+                                                             const long long* __restrict__ tile_off,
+                                                             IdxC* __restrict__ c_rp) {
+    __shared__ long long s_red[kScanThreads / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = (base + j < m) ? rnnz[base + j] : 0;
+        s += v[j];
+    }
+    long long total;
+    long long run = tile_off[blockIdx.x] + block_excl_scan_i64<kScanThreads>(s, s_red, &total);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < m) c_rp[base + j] = (IdxC)run;
+        run += v[j];
+    }
+}
+
+// Zeroes the counters (a kernel rather than a memset, so the sequence can be
+// captured in a graph).
+__global__ void k_zero_counters(Counters* ctr) {
+    uint32_t* p = reinterpret_cast<uint32_t*>(ctr);
+    for (int x = threadIdx.x; x < (int)(sizeof(Counters) / 4); x += blockDim.x) p[x] = 0u;
+}
+
+__global__ void k_reset_numeric(Counters* ctr) { ctr->group_next_num = 0u; }
+
+}  // namespace reap

@@ -1,0 +1,66 @@
+// Types shared by the SpGEMM kernels and the host plan.
+#pragma once
+#include <stdint.h>
+
+namespace reap {
+
+// Row classes, decided by the symbolic pass from the row's partial-product
+// count P_i, its number of A entries, its column window and nnz(C_i).
+enum RowClass : uint8_t {
+    kClsEmpty = 0,   // P_i = 0: the row of C is empty
+    kClsWaveBmpS = 1,  // one wavefront, bitmap window <= kWaveSmallWords words, nnz <= small cap
+    kClsWaveBmpL = 2,  // one wavefront, bitmap window <= kWaveBitsWords words, nnz <= 1024
+    kClsWaveHash = 3,  // one wavefront, LDS hash table (window too wide for a bitmap)
+    kClsGroup = 4,     // one workgroup: long rows
+    kNumClasses = 5
+};
+
+constexpr int kWaveMaxProducts = 1024;   // products per wavefront row (16 per lane)
+constexpr int kWaveMaxIt = kWaveMaxProducts / 64;
+constexpr int kWaveBitsWords = 1024;     // 32768-column window
+constexpr int kWaveSmallWords = 640;     // 20480-column window for the small numeric class
+constexpr int kWaveSmallNnz = 128;
+constexpr int kWaveLargeNnz = 1024;
+constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products
+constexpr int kWaveHashSlots = 512;      // load factor <= 1/2
+constexpr int kWaveHashIt = kWaveHashProducts / 64;
+constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap per workgroup
+constexpr int kGroupLdsValues = 8192;    // values a workgroup accumulates in LDS
+constexpr int kGroupMaskWords = 128;     // segment-start mask: 64 entries x 63 products
+constexpr int kRowsPerWave = 16;         // consecutive rows a wavefront walks through
+
+// Per-workgroup partial statistics of the wavefront symbolic kernel.
+struct WGPart {
+    unsigned long long products;
+    unsigned int cls[kNumClasses];
+    unsigned int max_prod;
+    unsigned int max_nnz;
+    unsigned int pad;
+};
+
+// Device-side counters, copied to the host at the end of the symbolic pass.
+struct Counters {
+    unsigned long long products;   // total partial products
+    unsigned long long nnz;        // nnz(C)
+    unsigned long long cls[8];     // rows per class
+    unsigned int max_prod;         // max partial products in one row (saturating)
+    unsigned int max_nnz;          // max nnz of one row of C
+    unsigned int n_group;          // length of the long-row list
+    unsigned int group_next;       // work counter of the long-row symbolic kernel
+    unsigned int group_next_num;   // work counter of the long-row numeric kernel
+    unsigned int max_group_nnz;    // max nnz of a long row
+    unsigned int bad_csr;          // validation flags (bit 0: A, bit 1: B)
+    unsigned int pad[5];
+};
+
+// Thresholds of one plan (clamped to the kernel capacities above).
+struct Thresholds {
+    int wave_max_products;   // <= kWaveMaxProducts
+    int wave_max_span;       // <= 32 * kWaveBitsWords
+    int wave_hash_products;  // <= kWaveHashProducts
+    int wave_small_nnz;      // <= kWaveSmallNnz
+    int group_lds_span;      // <= 32 * kGroupBitsWords, multiple of 32
+    int group_lds_values;    // <= kGroupLdsValues
+};
+
+}  // namespace reap

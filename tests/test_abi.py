@@ -1,0 +1,75 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/reap_spgemm.h declares, and rejects bad arguments before any device
+call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "reap_spgemm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(reap_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2004_13907_amd import _capi, build
+    if build.is_stale():
+        build.build()
+    return _capi.load()
+
+
+def test_header_declares_the_four_entry_points():
+    names = _declared()
+    for n in ("reap_spgemm_create", "reap_spgemm_symbolic", "reap_spgemm_numeric", "reap_spgemm_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2004_13907_amd import _capi
+    names = _declared()
+    assert sorted(_capi.EXPORTED) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert lib.reap_status_string(s)
+    assert lib.reap_status_string(99) == b"unknown status"
+    assert lib.reap_version() == b"0.1.0"
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    from paper_2004_13907_amd import _capi
+    assert lib.reap_spgemm_create(None, 1, 0, None, None) == _capi.REAP_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert lib.reap_spgemm_create(ctypes.byref(h), 7, 0, None, None) == _capi.REAP_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.reap_spgemm_create(ctypes.byref(h), 1, 5, None, None) == _capi.REAP_ERR_INVALID_ARG
+    assert lib.reap_spgemm_symbolic(None, None, None, None, None, None, None) == _capi.REAP_ERR_INVALID_ARG
+    assert lib.reap_spgemm_numeric(None, None, None, None, None, None) == _capi.REAP_ERR_INVALID_ARG
+    assert lib.reap_spgemm_destroy(None) == _capi.REAP_OK
+    assert lib.reap_spgemm_bin_stats(None, None) == _capi.REAP_ERR_INVALID_ARG
+    assert lib.reap_spgemm_phase_times(None, None, 0) == _capi.REAP_ERR_INVALID_ARG
+
+
+def test_struct_layout_matches_header():
+    from paper_2004_13907_amd import _capi
+    assert ctypes.sizeof(_capi.reap_csr_t) == 8 * 3 + 8 + 8 * 3
+    assert ctypes.sizeof(_capi.reap_options_t) == 16 * 4
+    assert ctypes.sizeof(_capi.reap_bin_stats_t) == 6 * 8
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2004_13907_amd import _capi
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_capi, "_lib", None)
+    with pytest.raises(RuntimeError):
+        _capi.load()
