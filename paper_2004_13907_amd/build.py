@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libreap_spgemm.so")
 SOURCES = ["reap_spgemm.hip"]
-HEADERS = ["device_utils.h", "spgemm_common.h", "kernels_symbolic.h", "kernels_numeric.h", "kernels_scan.h"]
+HEADERS = ["device_utils.h", "spgemm_common.h", "kernels_symbolic.h", "kernels_numeric.h", "kernels_scan.h",
+           "kernels_wave.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -26,6 +26,15 @@ __device__ __forceinline__ int mbcnt(uint64_t m) {
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Marks a value that is equal on all lanes as wave-uniform (scalar register).
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t uniform(int32_t v) { return uniform_i32(v); }
+__device__ __forceinline__ int64_t uniform(int64_t v) { return uniform_i64(v); }
+
 template <typename T>
 __device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, kWave); }
 
@@ -72,6 +81,50 @@ __device__ __forceinline__ long long wave_incl_scan_i64(long long v) {
         if (lane >= o) v += u;
     }
     return v;
+}
+
+// --- DPP (data-parallel primitive) wavefront scans and reductions ----------
+// Lanes are grouped in 4 rows of 16.  row_shr:n moves values n lanes up inside
+// a row; row_bcast:15 / row_bcast:31 broadcast lane 15 / 31 into the following
+// rows.  Out-of-range sources read 0 (or the identity passed as `old`).
+constexpr int kDppRowShr = 0x110;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int N>
+__device__ __forceinline__ int dpp_shr(int v, int id) {
+    return __builtin_amdgcn_update_dpp(id, v, kDppRowShr + N, 0xf, 0xf, false);
+}
+
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ int dpp_incl_scan(int v) {
+    v += dpp_shr<1>(v, 0);
+    v += dpp_shr<2>(v, 0);
+    v += dpp_shr<4>(v, 0);
+    v += dpp_shr<8>(v, 0);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowBcast15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowBcast31, 0xc, 0xf, false);
+    return v;
+}
+
+// Reductions whose result is returned to every lane (read from lane 63).
+__device__ __forceinline__ int dpp_reduce_sum(int v) {
+    return __builtin_amdgcn_readlane(dpp_incl_scan(v), kWave - 1);
+}
+
+__device__ __forceinline__ int dpp_reduce_max(int v) {  // for v >= INT32_MIN + 1
+    constexpr int id = INT32_MIN;
+    v = max(v, dpp_shr<1>(v, id));
+    v = max(v, dpp_shr<2>(v, id));
+    v = max(v, dpp_shr<4>(v, id));
+    v = max(v, dpp_shr<8>(v, id));
+    v = max(v, __builtin_amdgcn_update_dpp(id, v, kDppRowBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(id, v, kDppRowBcast31, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+__device__ __forceinline__ int dpp_reduce_min(int v) {
+    return -dpp_reduce_max(-v);  // v > INT32_MIN
 }
 
 // Exclusive scan over a workgroup of NT threads; returns this thread's

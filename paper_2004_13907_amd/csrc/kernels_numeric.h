@@ -2,7 +2,9 @@
 // the ascending-column write of each row of C (the multiply, sort and merge
 // steps of the paper's Algorithm 1).  Sorting is replaced by ranking: a bitmap
 // over the row's column window, with a prefix count per 32-bit word, gives
-// every column its position in the sorted row directly.
+// every column its position in the sorted row directly.  This file holds the
+// argument block and the long-row kernel; the wavefront kernels are in
+// kernels_wave.h.
 #pragma once
 #include "device_utils.h"
 #include "kernels_symbolic.h"
@@ -31,245 +33,6 @@ struct NumArgs {
     int64_t gvals_stride;   // doubles per workgroup slot
     Thresholds th;
 };
-
-// Loads the A entries of row i into the lanes of this wavefront and prepares
-// the flattened product index space: smask marks where each non-empty B row
-// starts, ebase[c] is the B index of product 0 of the c-th non-empty entry,
-// aval[c] its A value.  Returns P_i (at most kWaveMaxProducts).
-template <typename T, typename IdxT>
-__device__ __forceinline__ int wave_row_setup(const IdxT* __restrict__ a_rp, const int32_t* __restrict__ a_col,
-                                              const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
-                                              int64_t i, uint32_t* smask, IdxT* ebase, double* aval,
-                                              int smask_words) {
-    const int lane = lane_id();
-    const IdxT rs = a_rp[i];
-    const int nA = (int)((int64_t)a_rp[i + 1] - (int64_t)rs);
-    int64_t b0 = 0;
-    int len = 0;
-    double a = 0.0;
-    if (lane < nA) {
-        const int k = a_col[rs + lane];
-        const IdxT x0 = b_rp[k];
-        const IdxT x1 = b_rp[k + 1];
-        b0 = (int64_t)x0;
-        len = (int)((int64_t)x1 - (int64_t)x0);
-        a = (double)a_val[rs + lane];
-    }
-    const int incl = wave_incl_scan_i32(len);
-    const int P = uniform_i32(shfl(incl, kWave - 1));
-    const int start = incl - len;
-    const bool ne = len > 0;
-    const int c = mbcnt(ballot(ne));
-    if (lane < smask_words) smask[lane] = 0u;
-    wave_sync();
-    if (ne) {
-        ebase[c] = (IdxT)(b0 - start);
-        aval[c] = a;
-        atomicOr(&smask[start >> 5], 1u << (start & 31));
-    }
-    wave_sync();
-    return P;
-}
-
-// Rows of one wavefront class: each wavefront scans kRowsPerWave consecutive
-// rows and processes those whose class is CLS, so rows stay in order and
-// neighbouring rows (which share B rows) run close together on one XCD.
-template <typename Fn>
-__device__ __forceinline__ void for_each_class_row(const uint8_t* __restrict__ cls, int64_t m, int W,
-                                                   uint8_t want, Fn&& fn) {
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
-    const bool mine = lane < kRowsPerWave && row0 + lane < m && cls[row0 + lane] == want;
-    uint64_t todo = ballot(mine);
-    while (todo) {
-        const int r = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        fn(row0 + r);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One wavefront per row, bitmap window of at most WMAX words, at most NCMAX
-// entries in the row of C.  Products are held in registers (16 per lane).
-template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int W>
-__global__ void __launch_bounds__(W * 64) k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
-    __shared__ uint32_t s_bits[W][WMAX];
-    __shared__ uint16_t s_pfx[W][WMAX];
-    __shared__ double s_vals[W][NCMAX];
-    __shared__ int32_t s_cols[W][NCMAX];
-    __shared__ uint32_t s_smask[W][kWaveMaxProducts / 32];
-    __shared__ IdxT s_ebase[W][kWave];
-    __shared__ double s_aval[W][kWave];
-
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    uint32_t* bits = s_bits[w];
-    uint16_t* pfx = s_pfx[w];
-    double* vals = s_vals[w];
-    int32_t* cols_l = s_cols[w];
-
-    for_each_class_row(p.cls, p.m, W, want, [&](int64_t i) {
-        const int P = wave_row_setup<T, IdxT>(p.a_rp, p.a_col, p.a_val, p.b_rp, i, s_smask[w], s_ebase[w],
-                                              s_aval[w], kWaveMaxProducts / 32);
-        const int2 wn = p.win[i];
-        const int lo = wn.x, nw = wn.y;
-        const IdxC cb = p.c_rp[i];
-        const int nc = (int)((int64_t)p.c_rp[i + 1] - (int64_t)cb);
-        for (int x = lane; x < nw; x += kWave) bits[x] = 0u;
-        for (int x = lane; x < nc; x += kWave) vals[x] = 0.0;
-        wave_sync();
-        const int nIt = (P + kWave - 1) / kWave;
-        int cols[kWaveMaxIt];
-        double prod[kWaveMaxIt];
-        int seen = 0;
-#pragma unroll
-        for (int t = 0; t < kWaveMaxIt; ++t) {
-            cols[t] = -1;
-            prod[t] = 0.0;
-            if (t < nIt) {
-                const uint64_t M = ((uint64_t)s_smask[w][2 * t + 1] << 32) | s_smask[w][2 * t];
-                const int own = seen + mbcnt(M) + (int)((M >> lane) & 1u) - 1;
-                seen += __popcll(M);
-                const int q = t * kWave + lane;
-                if (q < P) {
-                    const int64_t bidx = (int64_t)s_ebase[w][own] + q;
-                    const int col = p.b_col[bidx];
-                    prod[t] = s_aval[w][own] * (double)p.b_val[bidx];
-                    cols[t] = col;
-                    const int d = col - lo;
-                    atomicOr(&bits[d >> 5], 1u << (d & 31));
-                }
-            }
-        }
-        wave_sync();
-        // prefix count of set bits per word: lane l owns words [l*per, l*per + per)
-        const int per = (nw + kWave - 1) / kWave;
-        const int w0 = min(lane * per, nw), w1 = min(w0 + per, nw);
-        int local = 0;
-        for (int x = w0; x < w1; ++x) local += __popc(bits[x]);
-        int run = wave_incl_scan_i32(local) - local;
-        for (int x = w0; x < w1; ++x) {
-            pfx[x] = (uint16_t)run;
-            run += __popc(bits[x]);
-        }
-        wave_sync();
-#pragma unroll
-        for (int t = 0; t < kWaveMaxIt; ++t) {
-            if (cols[t] >= 0) {
-                const int d = cols[t] - lo;
-                const int x = d >> 5;
-                const int r = pfx[x] + __popc(bits[x] & ((1u << (d & 31)) - 1u));
-                if (r < nc) {  // always true when the pattern matches the symbolic pass
-                    atomicAdd(&vals[r], prod[t]);
-                    cols_l[r] = cols[t];
-                }
-            }
-        }
-        wave_sync();
-        for (int x = lane; x < nc; x += kWave) {
-            p.c_col[(int64_t)cb + x] = cols_l[x];
-            p.c_val[(int64_t)cb + x] = (T)vals[x];
-        }
-        wave_sync();
-    });
-}
-
-// ---------------------------------------------------------------------------
-// One wavefront per row whose column window is too wide for a bitmap (at most
-// kWaveHashProducts products): LDS hash table keyed by column, then the
-// occupied slots are compacted and each entry is placed by counting the
-// smaller columns.
-template <typename T, typename IdxT, typename IdxC, int W>
-__global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
-    __shared__ uint32_t s_keys[W][kWaveHashSlots];
-    __shared__ double s_hv[W][kWaveHashSlots];
-    __shared__ int32_t s_ck[W][kWaveHashProducts];
-    __shared__ double s_cv[W][kWaveHashProducts];
-    __shared__ uint32_t s_smask[W][kWaveHashProducts / 32];
-    __shared__ IdxT s_ebase[W][kWave];
-    __shared__ double s_aval[W][kWave];
-
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    uint32_t* keys = s_keys[w];
-    double* hv = s_hv[w];
-    int32_t* ck = s_ck[w];
-    double* cv = s_cv[w];
-    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-
-    for_each_class_row(p.cls, p.m, W, want, [&](int64_t i) {
-        const int P = wave_row_setup<T, IdxT>(p.a_rp, p.a_col, p.a_val, p.b_rp, i, s_smask[w], s_ebase[w],
-                                              s_aval[w], kWaveHashProducts / 32);
-        const IdxC cb = p.c_rp[i];
-        for (int x = lane; x < kWaveHashSlots; x += kWave) {
-            keys[x] = kEmpty;
-            hv[x] = 0.0;
-        }
-        wave_sync();
-        const int nIt = (P + kWave - 1) / kWave;
-        int seen = 0;
-#pragma unroll
-        for (int t = 0; t < kWaveHashIt; ++t) {
-            if (t < nIt) {
-                const uint64_t M = ((uint64_t)s_smask[w][2 * t + 1] << 32) | s_smask[w][2 * t];
-                const int own = seen + mbcnt(M) + (int)((M >> lane) & 1u) - 1;
-                seen += __popcll(M);
-                const int q = t * kWave + lane;
-                if (q < P) {
-                    const int64_t bidx = (int64_t)s_ebase[w][own] + q;
-                    const int col = p.b_col[bidx];
-                    const double v = s_aval[w][own] * (double)p.b_val[bidx];
-                    const uint32_t key = (uint32_t)col;
-                    uint32_t h = hash_col(col) >> (32 - 9);
-                    while (true) {
-                        const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
-                        if (old == kEmpty || old == key) break;
-                        h = (h + 1) & (kWaveHashSlots - 1);
-                    }
-                    atomicAdd(&hv[h], v);
-                }
-            }
-        }
-        wave_sync();
-        int nc = 0;
-        for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
-            const int x = x0 + lane;
-            const bool occ = keys[x] != kEmpty;
-            const uint64_t bm = ballot(occ);
-            if (occ) {
-                const int pos = nc + mbcnt(bm);
-                ck[pos] = (int32_t)keys[x];
-                cv[pos] = hv[x];
-            }
-            nc += __popcll(bm);
-        }
-        wave_sync();
-        int key[kWaveHashIt];
-        int rank[kWaveHashIt];
-#pragma unroll
-        for (int u = 0; u < kWaveHashIt; ++u) {
-            const int e = u * kWave + lane;
-            key[u] = (e < nc) ? ck[e] : INT32_MAX;
-            rank[u] = 0;
-        }
-        for (int j = 0; j < nc; ++j) {
-            const int kj = ck[j];
-#pragma unroll
-            for (int u = 0; u < kWaveHashIt; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kWaveHashIt; ++u) {
-            const int e = u * kWave + lane;
-            if (e < nc) {
-                p.c_col[(int64_t)cb + rank[u]] = key[u];
-                p.c_val[(int64_t)cb + rank[u]] = (T)cv[e];
-            }
-        }
-        wave_sync();
-    });
-}
 
 // ---------------------------------------------------------------------------
 // Long rows: one workgroup per row (atomic work counter over the long-row

@@ -25,180 +25,6 @@ struct SymArgs {
 };
 
 // ---------------------------------------------------------------------------
-// One wavefront per row; each wavefront walks kRowsPerWave consecutive rows.
-// A row stays here when it has at most 64 entries in A and at most
-// th.wave_max_products partial products; its products are flattened over the
-// 64 lanes (16 per lane at most) and held in registers.  The distinct columns
-// are counted with an LDS bitmap over the row's column window [min, max], or,
-// when that window is wider than th.wave_max_span, with an LDS hash set.
-// Rows that do not fit are appended to the long-row list.
-template <typename IdxT>
-__global__ void __launch_bounds__(256) k_sym_wave(SymArgs<IdxT> p) {
-    constexpr int W = 4;
-    __shared__ uint32_t s_bits[W][kWaveBitsWords];
-    __shared__ uint32_t s_smask[W][kWaveMaxProducts / 32];
-    __shared__ IdxT s_ebase[W][kWave];
-    __shared__ WGPart s_part[W];
-
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
-    uint32_t* bits = s_bits[w];
-    uint32_t* smask = s_smask[w];
-    IdxT* ebase = s_ebase[w];
-
-    unsigned long long prod_acc = 0;
-    unsigned int cnt[kNumClasses] = {0, 0, 0, 0, 0};
-    unsigned int maxp = 0, maxn = 0;
-    uint32_t group_flags = 0;
-
-    for (int r = 0; r < kRowsPerWave; ++r) {
-        const int64_t i = row0 + r;
-        if (i >= p.m) break;
-        const IdxT rs = p.a_rp[i];
-        const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
-        uint8_t cls = kClsGroup;
-        int nnz = 0;
-        int2 win = make_int2(0, 0);
-        if (nA == 0) {
-            cls = kClsEmpty;
-        } else if (nA <= kWave) {
-            int64_t b0 = 0;
-            int len = 0;
-            if (lane < nA) {
-                const int k = p.a_col[rs + lane];
-                const IdxT x0 = p.b_rp[k];
-                const IdxT x1 = p.b_rp[k + 1];
-                b0 = (int64_t)x0;
-                len = (int)min((int64_t)x1 - (int64_t)x0, (int64_t)(1 << 24));
-            }
-            const int incl = wave_incl_scan_i32(len);
-            const int P = uniform_i32(shfl(incl, kWave - 1));
-            if (P == 0) {
-                cls = kClsEmpty;
-            } else if (P <= p.th.wave_max_products) {
-                const int start = incl - len;
-                const bool ne = len > 0;
-                const int c = mbcnt(ballot(ne));
-                if (lane < kWaveMaxProducts / 32) smask[lane] = 0u;
-                wave_sync();
-                if (ne) {
-                    ebase[c] = (IdxT)(b0 - start);
-                    atomicOr(&smask[start >> 5], 1u << (start & 31));
-                }
-                wave_sync();
-                const int nIt = (P + kWave - 1) / kWave;
-                int cols[kWaveMaxIt];
-                int cmin = INT32_MAX, cmax = -1, seen = 0;
-#pragma unroll
-                for (int t = 0; t < kWaveMaxIt; ++t) {
-                    cols[t] = -1;
-                    if (t < nIt) {
-                        const uint64_t M = ((uint64_t)smask[2 * t + 1] << 32) | smask[2 * t];
-                        const int own = seen + mbcnt(M) + (int)((M >> lane) & 1u) - 1;
-                        seen += __popcll(M);
-                        const int q = t * kWave + lane;
-                        if (q < P) {
-                            const int col = p.b_col[(int64_t)ebase[own] + q];
-                            cols[t] = col;
-                            cmin = min(cmin, col);
-                            cmax = max(cmax, col);
-                        }
-                    }
-                }
-                cmin = wave_min_i32(cmin);
-                cmax = wave_max_i32(cmax);
-                const int64_t span = (int64_t)cmax - cmin + 1;
-                if (span <= p.th.wave_max_span) {
-                    const int nw = (int)((span + 31) >> 5);
-                    for (int x = lane; x < nw; x += kWave) bits[x] = 0u;
-                    wave_sync();
-#pragma unroll
-                    for (int t = 0; t < kWaveMaxIt; ++t) {
-                        if (cols[t] >= 0) {
-                            const int d = cols[t] - cmin;
-                            atomicOr(&bits[d >> 5], 1u << (d & 31));
-                        }
-                    }
-                    wave_sync();
-                    int pc = 0;
-                    for (int x = lane; x < nw; x += kWave) pc += __popc(bits[x]);
-                    nnz = wave_sum_i32(pc);
-                    win = make_int2(cmin, nw);
-                    cls = (nnz <= p.th.wave_small_nnz && nw <= kWaveSmallWords) ? kClsWaveBmpS
-                                                                                : kClsWaveBmpL;
-                } else if (P <= p.th.wave_hash_products) {
-                    for (int x = lane; x < kWaveHashSlots; x += kWave) bits[x] = 0xFFFFFFFFu;
-                    wave_sync();
-                    int mine = 0;
-#pragma unroll
-                    for (int t = 0; t < kWaveHashIt; ++t) {
-                        if (cols[t] >= 0) {
-                            const uint32_t key = (uint32_t)cols[t];
-                            uint32_t h = hash_col(cols[t]) >> (32 - 9);
-                            while (true) {
-                                const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
-                                if (old == 0xFFFFFFFFu) { ++mine; break; }
-                                if (old == key) break;
-                                h = (h + 1) & (kWaveHashSlots - 1);
-                            }
-                        }
-                    }
-                    nnz = wave_sum_i32(mine);
-                    cls = kClsWaveHash;
-                }
-                wave_sync();
-                if (cls != kClsGroup) {
-                    prod_acc += (unsigned long long)P;
-                    maxp = max(maxp, (unsigned)P);
-                    maxn = max(maxn, (unsigned)nnz);
-                }
-            }
-        }
-        if (lane == 0) {
-            p.cls[i] = cls;
-            if (cls != kClsGroup) {
-                p.rnnz[i] = nnz;
-                p.win[i] = win;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < kNumClasses; ++c) cnt[c] += (cls == c) ? 1u : 0u;
-        if (cls == kClsGroup) group_flags |= 1u << r;
-    }
-
-    // append this wavefront's long rows with one atomic
-    if (group_flags) {
-        const bool mine = lane < kRowsPerWave && ((group_flags >> (lane & 31)) & 1u);
-        const uint64_t bm = ballot(mine);
-        int base = 0;
-        if (lane == 0) base = (int)atomicAdd(&p.ctr->n_group, (unsigned)__popcll(bm));
-        base = shfl(base, 0);
-        if (mine) p.group_rows[base + mbcnt(bm)] = (int32_t)(row0 + lane);
-    }
-
-    if (lane == 0) {
-        WGPart& s = s_part[w];
-        s.products = prod_acc;
-        for (int c = 0; c < kNumClasses; ++c) s.cls[c] = cnt[c];
-        s.max_prod = maxp;
-        s.max_nnz = maxn;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        WGPart t = s_part[0];
-        for (int v = 1; v < W; ++v) {
-            t.products += s_part[v].products;
-            for (int c = 0; c < kNumClasses; ++c) t.cls[c] += s_part[v].cls[c];
-            t.max_prod = max(t.max_prod, s_part[v].max_prod);
-            t.max_nnz = max(t.max_nnz, s_part[v].max_nnz);
-        }
-        p.parts[blockIdx.x] = t;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Enumerates the partial products of one row of A for one wavefront of a
 // workgroup.  The row's A entries are taken in chunks of 64 (chunk = wave,
 // wave + nwaves, ...).  Inside a chunk, entries whose B row is shorter than 64

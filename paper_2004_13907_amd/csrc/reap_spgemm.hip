@@ -12,6 +12,7 @@
 #include "kernels_numeric.h"
 #include "kernels_scan.h"
 #include "kernels_symbolic.h"
+#include "kernels_wave.h"
 #include "spgemm_common.h"
 
 using namespace reap;
@@ -274,13 +275,13 @@ reap_status_t run_numeric(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_
     ev_record(p, kPhNumWave, false);
     if (h.cls[kClsWaveBmpS] > 0) {
         const int blocks = (int)((m + kNumWavesS * kRowsPerWave - 1) / (kNumWavesS * kRowsPerWave));
-        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kNumWavesS>), dim3(blocks),
+        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS>), dim3(blocks),
                            dim3(kNumWavesS * kWave), 0, p->stream, a, (uint8_t)kClsWaveBmpS);
         REAP_LAUNCH_CHECK();
     }
     if (h.cls[kClsWaveBmpL] > 0) {
         const int blocks = (int)((m + kNumWavesL * kRowsPerWave - 1) / (kNumWavesL * kRowsPerWave));
-        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveLargeNnz, kWaveBitsWords, kNumWavesL>), dim3(blocks),
+        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveLargeNnz, kWaveBitsWords, kWaveMaxIt, kNumWavesL>), dim3(blocks),
                            dim3(kNumWavesL * kWave), 0, p->stream, a, (uint8_t)kClsWaveBmpL);
         REAP_LAUNCH_CHECK();
     }

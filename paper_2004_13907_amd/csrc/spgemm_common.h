@@ -8,7 +8,7 @@ namespace reap {
 // count P_i, its number of A entries, its column window and nnz(C_i).
 enum RowClass : uint8_t {
     kClsEmpty = 0,   // P_i = 0: the row of C is empty
-    kClsWaveBmpS = 1,  // one wavefront, bitmap window <= kWaveSmallWords words, nnz <= small cap
+    kClsWaveBmpS = 1,  // one wavefront, window <= kWaveSmallWords words, nnz <= small cap, <= 768 products
     kClsWaveBmpL = 2,  // one wavefront, bitmap window <= kWaveBitsWords words, nnz <= 1024
     kClsWaveHash = 3,  // one wavefront, LDS hash table (window too wide for a bitmap)
     kClsGroup = 4,     // one workgroup: long rows
@@ -20,6 +20,8 @@ constexpr int kWaveMaxIt = kWaveMaxProducts / 64;
 constexpr int kWaveBitsWords = 1024;     // 32768-column window
 constexpr int kWaveSmallWords = 640;     // 20480-column window for the small numeric class
 constexpr int kWaveSmallNnz = 128;
+constexpr int kWaveSmallProducts = 768;  // products of a small-class row (12 per lane)
+constexpr int kWaveSmallIt = 14;         // 64-lane steps of a small-class row (grouped mapping)
 constexpr int kWaveLargeNnz = 1024;
 constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products
 constexpr int kWaveHashSlots = 512;      // load factor <= 1/2
@@ -27,7 +29,8 @@ constexpr int kWaveHashIt = kWaveHashProducts / 64;
 constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap per workgroup
 constexpr int kGroupLdsValues = 8192;    // values a workgroup accumulates in LDS
 constexpr int kGroupMaskWords = 128;     // segment-start mask: 64 entries x 63 products
-constexpr int kRowsPerWave = 16;         // consecutive rows a wavefront walks through
+constexpr int kRowsPerWave = 8;          // consecutive rows a wavefront walks through
+constexpr int kStageCap = 256;           // A entries of one chunk of rows staged in LDS
 
 // Per-workgroup partial statistics of the wavefront symbolic kernel.
 struct WGPart {
