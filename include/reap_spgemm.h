@@ -81,11 +81,13 @@ typedef struct {
  *                        wavefront handles with a bitmap (<= 32768; 0 = default).
  *   wave_hash_products-- rows wider than that window but with at most this many
  *                        products use a wavefront hash table (<= 256; 0 = default).
- *   group_lds_span    -- widest window a workgroup keeps as a bitmap in LDS
- *                        (<= 262144; 0 = default); wider rows use device memory.
- *   group_lds_values  -- most entries a workgroup accumulates in LDS
- *                        (<= 8192; 0 = default); longer rows accumulate in
- *                        device memory.
+ *   group_lds_span    -- columns per segment of a long row's window: a long
+ *                        row's LDS bitmap covers this many columns at a time
+ *                        and wider windows are processed segment by segment
+ *                        (<= 262144, rounded down to a multiple of 32, at
+ *                        least 32; 0 = default 262144).
+ *   group_lds_values  -- accepted for compatibility and ignored: long rows
+ *                        accumulate their values in device memory.
  *   profile           -- non-zero: record per-phase device times (see
  *                        reap_spgemm_phase_times).
  *   wave_small_values -- rows of C with at most this many entries (and a

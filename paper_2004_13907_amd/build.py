@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libreap_spgemm.so")
 SOURCES = ["reap_spgemm.hip"]
 HEADERS = ["device_utils.h", "spgemm_common.h", "kernels_symbolic.h", "kernels_numeric.h", "kernels_scan.h",
-           "kernels_wave.h"]
+           "kernels_wave.h", "kernels_long.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -117,6 +117,4 @@ __global__ void k_zero_counters(Counters* ctr) {
     for (int x = threadIdx.x; x < (int)(sizeof(Counters) / 4); x += blockDim.x) p[x] = 0u;
 }
 
-__global__ void k_reset_numeric(Counters* ctr) { ctr->group_next_num = 0u; }
-
 }  // namespace reap

@@ -1,6 +1,7 @@
 // Wavefront-per-row kernels: symbolic (row product count, binning, per-row
 // column count) and numeric (products, accumulation, ascending-column write)
-// for rows with at most 64 entries in A and at most 1024 partial products.
+// for rows with at most 64 entries in A whose products fit the grouped lane
+// mapping below in a bounded number of 64-lane steps.
 //
 // Latency structure.  A wavefront owns a chunk of kRowsPerWave consecutive
 // rows.  The A entries of the whole chunk and the extents of the B rows they
@@ -9,11 +10,10 @@
 // and all of the row's B gathers are issued back to back before any of them
 // is consumed.
 //
-// Lane mapping of a row's products.  Grouped: G lanes (a power of two no
-// smaller than the row's longest B row) per A entry, 64/G entries per step;
-// the owner of a lane is a shift away.  Flattened (when grouping would need
-// too many steps): the products are numbered 0..P-1 over the lanes, and a bit
-// mask of segment starts plus a lane-mask popcount gives each lane its owner.
+// Lane mapping of a row's products: G lanes (a power of two no smaller than
+// the row's longest B row) per A entry, 64/G entries per step; the owner of a
+// lane is a shift away.  Rows whose B rows are longer than 64 entries, or that
+// would need more steps than the kernels hold, are long rows (kernels_long.h).
 #pragma once
 #include "device_utils.h"
 #include "kernels_numeric.h"
@@ -115,7 +115,7 @@ __device__ __forceinline__ void row_entries(const WaveStage<IdxT>& st, bool stag
 // One A entry as the product loops see it.
 template <typename IdxT>
 struct Ent {
-    IdxT b0;      // grouped: first B index of the entry; flattened: that minus the entry's first product
+    IdxT b0;      // first B index of the entry
     int32_t len;  // B row length
 };
 
@@ -124,60 +124,54 @@ template <typename IdxT>
 struct RowTable {
     Ent<IdxT> ent[kWave];
     double a[kWave];
-    uint32_t smask[kWaveMaxProducts / 32];
 };
 
 struct RowPlan {
     int P;       // partial products of the row
     int nIt;     // 64-lane steps
-    int logG;    // grouped: log2 of lanes per entry; -1: flattened
+    int logG;    // log2 of lanes per entry
     int nA;
 };
 
-// Chooses the lane mapping and writes the row's entry table.  Lanes >= nA
-// must carry len = 0.  `slot` receives this lane's index into tb.a (valid when
-// len > 0), to be written once the A value has arrived.
+// 64-lane steps of a row under the grouped mapping, or a number above every
+// step limit when a B row has more than 64 entries.  Lanes >= nA must carry
+// len = 0.
+__device__ __forceinline__ int grouped_steps(int nA, int len) {
+    const int maxlen = dpp_reduce_max(len);
+    const int logG = maxlen <= 1 ? 0 : 32 - __clz(maxlen - 1);
+    if (logG > 6) return kWaveMaxIt + 1;
+    const int shiftE = 6 - logG;
+    return (nA + (1 << shiftE) - 1) >> shiftE;
+}
+
+// Plans the grouped mapping and writes the row's entry table.  Lanes >= nA
+// must carry len = 0, and the classification guarantees at most MAXIT steps
+// (a longer plan is cut to MAXIT steps; the numeric pass then finds fewer
+// columns than the symbolic pass did and leaves the extra slots zero).
+// `slot` receives this lane's index into tb.a, to be written once the A value
+// has arrived.
 template <typename IdxT, int MAXIT>
 __device__ __forceinline__ RowPlan plan_row(int nA, IdxT b0, int len, RowTable<IdxT>& tb, int& slot) {
     const int lane = lane_id();
     RowPlan pl;
     pl.nA = nA;
-    const int incl = dpp_incl_scan(len);
-    pl.P = __builtin_amdgcn_readlane(incl, kWave - 1);
+    pl.P = dpp_reduce_sum(len);
     const int maxlen = dpp_reduce_max(len);
-    const int logG = maxlen <= 1 ? 0 : 32 - __clz(maxlen - 1);  // lanes per entry = 2^logG
-    const int shiftE = 6 - logG;                                  // entries per step = 2^shiftE
-    const int nItG = (logG <= 6) ? (nA + (1 << shiftE) - 1) >> shiftE : MAXIT + 1;
-    if (nItG <= MAXIT) {
-        pl.logG = logG;
-        pl.nIt = nItG;
-        slot = lane;
-        if (lane < nA) tb.ent[lane] = Ent<IdxT>{b0, len};
-    } else {
-        pl.logG = -1;
-        pl.nIt = (pl.P + kWave - 1) >> 6;
-        const int start = incl - len;
-        const bool ne = len > 0;
-        slot = mbcnt(ballot(ne));
-        if (lane < kWaveMaxProducts / 32) tb.smask[lane] = 0u;
-        wave_sync();
-        if (ne) {
-            tb.ent[slot] = Ent<IdxT>{(IdxT)(b0 - (IdxT)start), len};
-            atomicOr(&tb.smask[start >> 5], 1u << (start & 31));
-        }
-    }
+    pl.logG = min(maxlen <= 1 ? 0 : 32 - __clz(maxlen - 1), 6);  // lanes per entry = 2^logG
+    const int shiftE = 6 - pl.logG;                               // entries per step = 2^shiftE
+    pl.nIt = min((nA + (1 << shiftE) - 1) >> shiftE, MAXIT);
+    slot = lane;
+    if (lane < nA) tb.ent[lane] = Ent<IdxT>{b0, len};
     wave_sync();
     return pl;
 }
-
-enum { kMapGrouped = 0, kMapFlat = 1 };
 
 // Gathers a row's products for every step t < pl.nIt: ok[t] says whether this
 // lane holds a product, own[t] is its entry slot in tb, col[t] / bv[t] its B
 // column and value (VALS).  Lanes without a product load the row's first
 // product (`safe`, a valid index) so the loads need no branches; all loads are
 // issued before any is used.
-template <int MODE, bool VALS, typename T, typename IdxT, int MAXIT>
+template <bool VALS, typename T, typename IdxT, int MAXIT>
 __device__ __forceinline__ void row_gather(const RowTable<IdxT>& tb, const RowPlan& pl, IdxT safe,
                                            const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
                                            bool (&ok)[MAXIT], int (&own)[MAXIT], int (&col)[MAXIT],
@@ -186,44 +180,24 @@ __device__ __forceinline__ void row_gather(const RowTable<IdxT>& tb, const RowPl
     const int nIt = uniform_i32(pl.nIt);
     const int nA = uniform_i32(pl.nA);
     const int logG = uniform_i32(pl.logG);
-    const int P = uniform_i32(pl.P);
     IdxT bidx[MAXIT];
-    if (MODE == kMapGrouped) {
-        // group g of lanes takes entries g*nIt .. g*nIt + nIt - 1, so the entries
-        // side by side in one step are far apart in the row (their B rows share
-        // fewer columns, which keeps LDS atomics from colliding)
-        const int e0 = (lane >> logG) * nIt;
-        const int off = lane & ((1 << logG) - 1);
+    // group g of lanes takes entries g*nIt .. g*nIt + nIt - 1, so the entries
+    // side by side in one step are far apart in the row (their B rows share
+    // fewer columns, which keeps LDS atomics from colliding)
+    const int e0 = (lane >> logG) * nIt;
+    const int off = lane & ((1 << logG) - 1);
 #pragma unroll
-        for (int t = 0; t < MAXIT; ++t) {
-            ok[t] = false;
-            own[t] = 0;
-            bidx[t] = safe;
-            if (t < nIt) {
-                const int e = e0 + t;
-                const int ec = min(e, kWave - 1);
-                const Ent<IdxT> en = tb.ent[ec];
-                ok[t] = (e < nA) && (off < en.len);
-                own[t] = ec;
-                bidx[t] = ok[t] ? en.b0 + (IdxT)off : safe;
-            }
-        }
-    } else {
-        int seen = 0;
-#pragma unroll
-        for (int t = 0; t < MAXIT; ++t) {
-            ok[t] = false;
-            own[t] = 0;
-            bidx[t] = safe;
-            if (t < nIt) {
-                const uint64_t M = ((uint64_t)tb.smask[2 * t + 1] << 32) | tb.smask[2 * t];
-                const int o = max(seen + mbcnt(M) + (int)((M >> lane) & 1u) - 1, 0);
-                seen += __popcll(M);
-                const int q = t * kWave + lane;
-                ok[t] = q < P;
-                own[t] = o;
-                bidx[t] = ok[t] ? tb.ent[o].b0 + (IdxT)q : safe;
-            }
+    for (int t = 0; t < MAXIT; ++t) {
+        ok[t] = false;
+        own[t] = 0;
+        bidx[t] = safe;
+        if (t < nIt) {
+            const int e = e0 + t;
+            const int ec = min(e, kWave - 1);
+            const Ent<IdxT> en = tb.ent[ec];
+            ok[t] = (e < nA) && (off < en.len);
+            own[t] = ec;
+            bidx[t] = ok[t] ? en.b0 + (IdxT)off : safe;
         }
     }
 #pragma unroll
@@ -254,7 +228,7 @@ __device__ __forceinline__ IdxT row_safe_index(IdxT b0, int len) {
 // set in an LDS bitmap over the window (or, when the window is wider than
 // th.wave_max_span, inserted in an LDS hash set).  Lanes without a product set
 // a bit in the dummy word bits[kWaveBitsWords], so no lane needs a branch.
-template <int MODE, typename IdxT, int MAXIT>
+template <typename IdxT, int MAXIT>
 __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan& pl, IdxT safe,
                                         const int32_t* __restrict__ b_col, uint32_t* bits, const Thresholds& th,
                                         uint8_t& cls, int& nnz, int2& win) {
@@ -264,7 +238,7 @@ __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan&
     int own[MAXIT];
     int col[MAXIT];
     float bv_unused[MAXIT];
-    row_gather<MODE, false, float, IdxT, MAXIT>(tb, pl, safe, b_col, nullptr, ok, own, col, bv_unused);
+    row_gather<false, float, IdxT, MAXIT>(tb, pl, safe, b_col, nullptr, ok, own, col, bv_unused);
     int cmin = INT32_MAX, cmax = -1;
 #pragma unroll
     for (int t = 0; t < MAXIT; ++t) {
@@ -292,9 +266,11 @@ __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan&
         for (int x = lane; x < nw; x += kWave) pc += __popc(bits[pad_word(x)]);
         nnz = dpp_reduce_sum(pc);
         win = make_int2(cmin, nw);
-        cls = (nnz <= th.wave_small_nnz && nw <= kWaveSmallWords && uniform_i32(pl.P) <= kWaveSmallProducts) ? kClsWaveBmpS
-                                                                                                : kClsWaveBmpL;
-    } else if (uniform_i32(pl.P) <= th.wave_hash_products) {
+        // the compact bitmap class, or the long-row kernels
+        cls = (nnz <= th.wave_small_nnz && nw <= kWaveSmallWords && uniform_i32(pl.P) <= kWaveSmallProducts)
+                  ? kClsWaveBmpS
+                  : kClsGroup;
+    } else if (uniform_i32(pl.P) <= th.wave_hash_products && nIt <= kWaveHashIt) {
         for (int x = lane; x < kWaveHashSlots; x += kWave) bits[x] = 0xFFFFFFFFu;
         wave_sync();
         int mine = 0;
@@ -368,14 +344,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
             const int P = dpp_reduce_sum(len);
             if (P == 0) {
                 cls = kClsEmpty;
-            } else if (P <= p.th.wave_max_products) {
+            } else if (P <= p.th.wave_max_products && grouped_steps(nA, len) <= kWaveSmallIt) {
+                // the grouped lane mapping fits: the row stays with one wavefront
+                // (bitmap or hash); rows that would need the flattened mapping or
+                // the large bitmap class go to the long-row kernels
                 int slot_unused;
                 const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot_unused);
                 const IdxT safe = row_safe_index(b0, len);
-                if (uniform_i32(pl.logG) >= 0)
-                    sym_row<kMapGrouped, IdxT, MAXIT>(tb, pl, safe, p.b_col, bits, p.th, cls, nnz, win);
-                else
-                    sym_row<kMapFlat, IdxT, MAXIT>(tb, pl, safe, p.b_col, bits, p.th, cls, nnz, win);
+                sym_row<IdxT, MAXIT>(tb, pl, safe, p.b_col, bits, p.th, cls, nnz, win);
                 if (cls != kClsGroup) {
                     prod_acc += (unsigned long long)P;
                     maxp = max(maxp, (unsigned)P);
@@ -429,7 +405,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
 // counts, rank each product's column, accumulate, write the sorted row.
 // Lanes without a product aim at the dummy word bp[WMAX] and the dummy slot
 // vals[NCMAX], so no lane needs a branch.
-template <int MODE, typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT>
+template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT>
 __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int64_t i, RowTable<IdxT>& tb,
                                             const RowPlan& pl, IdxT safe, int slot, bool has_entry, T a,
                                             uint2* bp, double* vals, int32_t* cols_l) {
@@ -439,7 +415,7 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     int own[MAXIT];
     int col[MAXIT];
     T bv[MAXIT];
-    row_gather<MODE, true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
+    row_gather<true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
     const int2 wn = p.win[i];
     const int lo = uniform_i32(wn.x), nw = uniform_i32(wn.y);
     const int64_t cb = uniform((int64_t)p.c_rp[i]);
@@ -450,14 +426,14 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     wave_sync();
     int dd[MAXIT];
     double prod[MAXIT];
-    const int ge0 = (MODE == kMapGrouped) ? (lane >> uniform_i32(pl.logG)) * nIt : 0;
+    const int ge0 = (lane >> uniform_i32(pl.logG)) * nIt;
 #pragma unroll
     for (int t = 0; t < MAXIT; ++t) {
         if (t < nIt) {
             const int d = ok[t] ? col[t] - lo : WMAX * 32;
             dd[t] = d;
             atomicOr(&bp[pad_word(d >> 5)].x, 1u << (d & 31));
-            const int ow = (MODE == kMapGrouped) ? min(ge0 + t, kWave - 1) : own[t];
+            const int ow = min(ge0 + t, kWave - 1);
             prod[t] = tb.a[ow] * (double)bv[t];
         }
     }
@@ -535,12 +511,7 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
         int slot;
         const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot);
         const IdxT safe = row_safe_index(b0, len);
-        if (uniform_i32(pl.logG) >= 0)
-            num_row_bmp<kMapGrouped, T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bp,
-                                                                       vals, cols_l);
-        else
-            num_row_bmp<kMapFlat, T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bp, vals,
-                                                                    cols_l);
+        num_row_bmp<T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bp, vals, cols_l);
     }
 }
 
@@ -593,10 +564,7 @@ __global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC>
         int own[MAXIT];
         int col[MAXIT];
         T bv[MAXIT];
-        if (uniform_i32(pl.logG) >= 0)
-            row_gather<kMapGrouped, true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
-        else
-            row_gather<kMapFlat, true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
+        row_gather<true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
         const int64_t cb = uniform((int64_t)p.c_rp[i]);
         if (len > 0) tb.a[slot] = (double)a;
         for (int x = lane; x < kWaveHashSlots; x += kWave) {

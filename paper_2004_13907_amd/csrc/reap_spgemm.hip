@@ -5,10 +5,12 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
 #include "../../include/reap_spgemm.h"
+#include "kernels_long.h"
 #include "kernels_numeric.h"
 #include "kernels_scan.h"
 #include "kernels_symbolic.h"
@@ -37,6 +39,7 @@ struct reap_spgemm_s {
     Thresholds th{};
     bool validate = false;
     bool profile = false;
+    bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
 
     Workspace ws;          // per-row arrays, counters, partials
     Workspace gvals;       // long-row FP64 accumulators (FP32 output only)
@@ -73,7 +76,6 @@ namespace {
 
 constexpr int kSymWaves = 4;
 constexpr int kNumWavesS = 4;
-constexpr int kNumWavesL = 2;
 constexpr int kNumWavesH = 4;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -152,6 +154,17 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t m) {
     return REAP_OK;
 }
 
+// With REAP_DEBUG_SYNC=1 in the environment every kernel launch is followed by
+// a stream synchronisation and a line on stderr, so a failing kernel is named.
+void debug_step(reap_spgemm_s* p, const char* kernel) {
+    if (!p->debug_sync) return;
+    fprintf(stderr, "[reap] %s launched\n", kernel);
+    fflush(stderr);
+    const hipError_t e = hipStreamSynchronize(p->stream);
+    fprintf(stderr, "[reap] %s done (%s)\n", kernel, hipGetErrorString(e));
+    fflush(stderr);
+}
+
 void ev_record(reap_spgemm_s* p, int phase, bool end) {
     if (p->profile && p->events_ok) {
         (void)hipEventRecord(p->ev[2 * phase + (end ? 1 : 0)], p->stream);
@@ -201,15 +214,19 @@ reap_status_t run_symbolic(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr
     if (sym_blocks > 0) {
         hipLaunchKernelGGL(k_sym_wave<IdxT>, dim3(sym_blocks), dim3(kSymWaves * kWave), 0, p->stream, a);
         REAP_LAUNCH_CHECK();
-        const int ggrid = std::max(1, p->num_cus * 3);
-        hipLaunchKernelGGL(k_sym_group<IdxT>, dim3(ggrid), dim3(512), 0, p->stream, a);
+        debug_step(p, "k_sym_wave");
+        // the long-row count is known on the device only: a fixed grid walks the list
+        const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)p->num_cus * 2));
+        hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a);
         REAP_LAUNCH_CHECK();
+        debug_step(p, "k_long_sym");
     }
     ev_record(p, kPhSymbolic, true);
     ev_record(p, kPhScan, false);
     if (ntiles > 0) {
         hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, p->stream, p->rnnz, m, p->tiles);
         REAP_LAUNCH_CHECK();
+        debug_step(p, "k_scan_tiles");
     }
     if (p->cidx == REAP_I32) {
         hipLaunchKernelGGL(k_scan_spine<int32_t>, dim3(1), dim3(1024), 0, p->stream, p->tiles, ntiles, p->parts,
@@ -270,20 +287,13 @@ reap_status_t run_numeric(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_
     const Counters& h = *p->h_ctr;
 
     ev_record(p, kPhNumAll, false);
-    hipLaunchKernelGGL(k_reset_numeric, dim3(1), dim3(1), 0, p->stream, p->ctr);
-    REAP_LAUNCH_CHECK();
     ev_record(p, kPhNumWave, false);
     if (h.cls[kClsWaveBmpS] > 0) {
         const int blocks = (int)((m + kNumWavesS * kRowsPerWave - 1) / (kNumWavesS * kRowsPerWave));
         hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS>), dim3(blocks),
                            dim3(kNumWavesS * kWave), 0, p->stream, a, (uint8_t)kClsWaveBmpS);
         REAP_LAUNCH_CHECK();
-    }
-    if (h.cls[kClsWaveBmpL] > 0) {
-        const int blocks = (int)((m + kNumWavesL * kRowsPerWave - 1) / (kNumWavesL * kRowsPerWave));
-        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveLargeNnz, kWaveBitsWords, kWaveMaxIt, kNumWavesL>), dim3(blocks),
-                           dim3(kNumWavesL * kWave), 0, p->stream, a, (uint8_t)kClsWaveBmpL);
-        REAP_LAUNCH_CHECK();
+        debug_step(p, "k_num_wave_bmp (small)");
     }
     ev_record(p, kPhNumWave, true);
     ev_record(p, kPhNumHash, false);
@@ -292,12 +302,14 @@ reap_status_t run_numeric(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_
         hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH>), dim3(blocks), dim3(kNumWavesH * kWave), 0,
                            p->stream, a, (uint8_t)kClsWaveHash);
         REAP_LAUNCH_CHECK();
+        debug_step(p, "k_num_wave_hash");
     }
     ev_record(p, kPhNumHash, true);
     ev_record(p, kPhNumGroup, false);
     if (h.n_group > 0) {
-        hipLaunchKernelGGL((k_num_group<T, IdxT, IdxC>), dim3(p->group_grid), dim3(1024), 0, p->stream, a);
+        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->group_grid), dim3(kLongThreads), 0, p->stream, a);
         REAP_LAUNCH_CHECK();
+        debug_step(p, "k_long_num");
     }
     ev_record(p, kPhNumGroup, true);
     ev_record(p, kPhNumAll, true);
@@ -339,12 +351,13 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     if (opts) o = *opts;
     p->validate = o.validate != 0;
     p->profile = o.profile != 0;
+    const char* dbg = std::getenv("REAP_DEBUG_SYNC");
+    p->debug_sync = dbg && dbg[0] == '1';
     p->th.wave_max_products = clampi(o.wave_max_products, 0, kWaveMaxProducts, kWaveMaxProducts);
     p->th.wave_max_span = clampi(o.wave_max_span, 0, 32 * kWaveBitsWords, 32 * kWaveBitsWords);
     p->th.wave_hash_products = clampi(o.wave_hash_products, 0, kWaveHashProducts, kWaveHashProducts);
     p->th.wave_small_nnz = clampi(o.wave_small_values, 0, kWaveSmallNnz, kWaveSmallNnz);
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
-    p->th.group_lds_values = clampi(o.group_lds_values, 0, kGroupLdsValues, kGroupLdsValues);
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -413,11 +426,13 @@ reap_status_t reap_spgemm_symbolic(reap_spgemm_t p, const reap_csr_t* A, const r
     const Counters& h = *p->h_ctr;
     const int64_t nnz = (int64_t)h.nnz;
 
-    // long-row FP64 accumulators for FP32 output when a row exceeds the LDS capacity
-    p->group_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h.n_group, p->num_cus));
+    // long rows: one workgroup per list entry up to two per CU; FP32 output
+    // needs an FP64 accumulator per workgroup (one segment of the widest row)
+    p->group_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h.n_group, (int64_t)p->num_cus * 2));
     p->gvals_stride = 0;
-    if (p->dtype == REAP_F32 && h.n_group > 0 && (int64_t)h.max_group_nnz > p->th.group_lds_values) {
-        const int64_t stride = std::min<int64_t>((int64_t)h.max_group_nnz, (int64_t)p->th.group_lds_span);
+    if (p->dtype == REAP_F32 && h.n_group > 0) {
+        const int64_t stride =
+            std::max<int64_t>(1, std::min<int64_t>((int64_t)h.max_group_nnz, (int64_t)p->th.group_lds_span));
         const size_t need = (size_t)stride * (size_t)p->group_grid * sizeof(double);
         if (need > p->gvals.bytes) {
             if (p->gvals.base) (void)hipFree(p->gvals.base);

@@ -9,7 +9,7 @@ namespace reap {
 enum RowClass : uint8_t {
     kClsEmpty = 0,   // P_i = 0: the row of C is empty
     kClsWaveBmpS = 1,  // one wavefront, window <= kWaveSmallWords words, nnz <= small cap, <= 768 products
-    kClsWaveBmpL = 2,  // one wavefront, bitmap window <= kWaveBitsWords words, nnz <= 1024
+    kClsWaveBmpL = 2,  // not produced (rows past the compact class are long rows)
     kClsWaveHash = 3,  // one wavefront, LDS hash table (window too wide for a bitmap)
     kClsGroup = 4,     // one workgroup: long rows
     kNumClasses = 5
@@ -22,13 +22,10 @@ constexpr int kWaveSmallWords = 640;     // 20480-column window for the small nu
 constexpr int kWaveSmallNnz = 128;
 constexpr int kWaveSmallProducts = 768;  // products of a small-class row (12 per lane)
 constexpr int kWaveSmallIt = 14;         // 64-lane steps of a small-class row (grouped mapping)
-constexpr int kWaveLargeNnz = 1024;
 constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products
 constexpr int kWaveHashSlots = 512;      // load factor <= 1/2
 constexpr int kWaveHashIt = kWaveHashProducts / 64;
-constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap per workgroup
-constexpr int kGroupLdsValues = 8192;    // values a workgroup accumulates in LDS
-constexpr int kGroupMaskWords = 128;     // segment-start mask: 64 entries x 63 products
+constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap segment of a long row
 constexpr int kRowsPerWave = 8;          // consecutive rows a wavefront walks through
 constexpr int kStageCap = 256;           // A entries of one chunk of rows staged in LDS
 
@@ -49,8 +46,8 @@ struct Counters {
     unsigned int max_prod;         // max partial products in one row (saturating)
     unsigned int max_nnz;          // max nnz of one row of C
     unsigned int n_group;          // length of the long-row list
-    unsigned int group_next;       // work counter of the long-row symbolic kernel
-    unsigned int group_next_num;   // work counter of the long-row numeric kernel
+    unsigned int unused0;
+    unsigned int unused1;
     unsigned int max_group_nnz;    // max nnz of a long row
     unsigned int bad_csr;          // validation flags (bit 0: A, bit 1: B)
     unsigned int pad[5];
@@ -63,7 +60,6 @@ struct Thresholds {
     int wave_hash_products;  // <= kWaveHashProducts
     int wave_small_nnz;      // <= kWaveSmallNnz
     int group_lds_span;      // <= 32 * kGroupBitsWords, multiple of 32
-    int group_lds_values;    // <= kGroupLdsValues
 };
 
 }  // namespace reap
