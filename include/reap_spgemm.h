@@ -93,6 +93,13 @@ typedef struct {
  *   wave_small_values -- rows of C with at most this many entries (and a
  *                        window of at most 20480 columns) use the compact
  *                        wavefront kernel (<= 128; 0 = default 128).
+ *   graph             -- non-zero: each symbolic and numeric call is captured
+ *                        into a HIP graph the first time its launch shape
+ *                        occurs and replayed while the shape repeats (one
+ *                        graph launch per call instead of one launch per
+ *                        kernel).  Needs a stream other than the legacy
+ *                        default stream; ignored with `validate` or with
+ *                        REAP_DEBUG_SYNC=1 in the environment.
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -104,7 +111,8 @@ typedef struct {
     int32_t group_lds_values;
     int32_t profile;
     int32_t wave_small_values;
-    int32_t reserved[8];
+    int32_t graph;
+    int32_t reserved[7];
 } reap_options_t;
 
 /* Per-class row counts of the last symbolic pass (how rows were binned). */
@@ -158,6 +166,32 @@ reap_status_t reap_spgemm_symbolic(reap_spgemm_t plan, const reap_csr_t* A, cons
  */
 reap_status_t reap_spgemm_numeric(reap_spgemm_t plan, const reap_csr_t* A, const reap_csr_t* B,
                                   const void* c_row_ptr, int32_t* c_col_idx, void* c_values);
+
+/*
+ * Batched symbolic pass: `count` independent products C_q = A_q * B_q in one
+ * launch per kernel (every product's rows share the wavefront kernels' grid;
+ * the long rows of all products share one list).  A, B: host arrays of
+ * `count` descriptors, all with the same row-pointer type; c_row_ptr: host
+ * array of `count` device pointers (A_q.rows + 1 elements each).  c_nnz
+ * (required) and n_products (optional): host arrays of `count` entries.
+ * The per-product semantics are those of reap_spgemm_symbolic; a plan holds
+ * the state of its last call, single or batched.  Blocks until every nnz(C_q)
+ * is known.  Errors: as reap_spgemm_symbolic (INDEX_OVERFLOW if any product
+ * overflows an int32 C row pointer).
+ */
+reap_status_t reap_spgemm_batch_symbolic(reap_spgemm_t plan, int64_t count, const reap_csr_t* A,
+                                         const reap_csr_t* B, void* const* c_row_ptr, int64_t* c_nnz,
+                                         int64_t* n_products, size_t* workspace_bytes);
+
+/*
+ * Batched numeric pass after reap_spgemm_batch_symbolic with the same count,
+ * shapes and patterns (values may differ).  c_row_ptr, c_col_idx, c_values:
+ * host arrays of `count` device pointers (nnz(C_q) column indices and values
+ * each).  Asynchronous.  Errors: as reap_spgemm_numeric.
+ */
+reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t plan, int64_t count, const reap_csr_t* A,
+                                        const reap_csr_t* B, const void* const* c_row_ptr,
+                                        int32_t* const* c_col_idx, void* const* c_values);
 
 /* Release the plan's workspace and the plan (NULL is accepted). */
 reap_status_t reap_spgemm_destroy(reap_spgemm_t plan);

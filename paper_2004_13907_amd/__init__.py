@@ -24,10 +24,14 @@ __all__ = [
     "DeviceCSR",
     "SpGEMMError",
     "Plan",
+    "Batch",
     "spgemm",
+    "spgemm_batch",
     "reap_spgemm_create",
     "reap_spgemm_symbolic",
     "reap_spgemm_numeric",
+    "reap_spgemm_batch_symbolic",
+    "reap_spgemm_batch_numeric",
     "reap_spgemm_destroy",
     "reap_spgemm_bin_stats",
     "reap_spgemm_phase_times",
@@ -171,6 +175,33 @@ def reap_spgemm_numeric(plan, A: DeviceCSR, B: DeviceCSR, c_row_ptr: torch.Tenso
                                    ctypes.c_void_p(c_val.data_ptr() if c_val.numel() else None))
 
 
+def reap_spgemm_batch_symbolic(plan, As, Bs, c_row_ptrs):
+    """Returns (status, [nnz(C_q)], [partial products of q], workspace bytes)."""
+    lib = _capi.load()
+    n = len(As)
+    if len(Bs) != n or len(c_row_ptrs) != n:
+        raise ValueError("A, B and C row-pointer lists differ in length")
+    a = (reap_csr_t * n)(*[x.c_struct() for x in As])
+    b = (reap_csr_t * n)(*[x.c_struct() for x in Bs])
+    rp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in c_row_ptrs])
+    nnz = (ctypes.c_int64 * n)()
+    prods = (ctypes.c_int64 * n)()
+    ws = ctypes.c_size_t(0)
+    st = lib.reap_spgemm_batch_symbolic(plan, n, a, b, rp, nnz, prods, ctypes.byref(ws))
+    return st, [int(x) for x in nnz], [int(x) for x in prods], int(ws.value)
+
+
+def reap_spgemm_batch_numeric(plan, As, Bs, c_row_ptrs, c_cols, c_vals) -> int:
+    lib = _capi.load()
+    n = len(As)
+    a = (reap_csr_t * n)(*[x.c_struct() for x in As])
+    b = (reap_csr_t * n)(*[x.c_struct() for x in Bs])
+    rp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in c_row_ptrs])
+    cc = (ctypes.c_void_p * n)(*[(t.data_ptr() if t.numel() else None) for t in c_cols])
+    cv = (ctypes.c_void_p * n)(*[(t.data_ptr() if t.numel() else None) for t in c_vals])
+    return lib.reap_spgemm_batch_numeric(plan, n, a, b, rp, cc, cv)
+
+
 def reap_spgemm_destroy(plan) -> int:
     return _capi.load().reap_spgemm_destroy(plan)
 
@@ -268,6 +299,109 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Independent products C_q = A_q * B_q computed together: one launch per
+    kernel for the whole batch, or, with ``graph=True``, one HIP graph launch
+    per pass, captured on first use and replayed while the batch's launch
+    shape repeats.  C's row pointers, columns and values live in three device
+    buffers; the results are views into them.  Work runs on ``stream`` (a
+    fresh torch stream when ``graph`` is set and none is given)."""
+
+    def __init__(self, dtype=torch.float64, c_index_dtype=torch.int32, stream=None, graph: bool = False,
+                 **options):
+        if graph and stream is None:
+            stream = torch.cuda.Stream()
+        self.stream = stream
+        self.dtype = dtype
+        self.c_index_dtype = c_index_dtype
+        self.plan = Plan(dtype, c_index_dtype, stream=stream, graph=int(bool(graph)), **options)
+        self.nnz = []
+        self.products = []
+        self.workspace_bytes = 0
+        self._rp = None
+        self._rp_views = []
+
+    def _ctx(self):
+        return torch.cuda.stream(self.stream) if self.stream is not None else _NullCtx()
+
+    def symbolic(self, As, Bs):
+        """Per-product nnz(C_q); row pointers are written on the device."""
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many (and at least one) A and B operands")
+        for A, B in zip(As, Bs):
+            self.plan._check_dtypes(A, B)
+        total = sum(A.rows + 1 for A in As)
+        dev = As[0].row_ptr.device
+        with self._ctx():
+            if self._rp is None or self._rp.numel() < total or self._rp.dtype != self.c_index_dtype:
+                self._rp = torch.empty(total, dtype=self.c_index_dtype, device=dev)
+        views, o = [], 0
+        for A in As:
+            views.append(self._rp[o:o + A.rows + 1])
+            o += A.rows + 1
+        st, nnz, prods, ws = reap_spgemm_batch_symbolic(self.plan.handle, As, Bs, views)
+        if st != REAP_OK:
+            raise SpGEMMError(st, "reap_spgemm_batch_symbolic")
+        self._rp_views = views
+        self.nnz, self.products, self.workspace_bytes = nnz, prods, ws
+        return nnz
+
+    def numeric(self, As, Bs, out=None):
+        """Writes every C_q; returns the list of DeviceCSR results (views into
+        the batch's buffers, or into ``out`` = (col, val) buffers of at least
+        sum(nnz) elements).  Asynchronous on the batch's stream."""
+        total = sum(self.nnz)
+        dev = As[0].row_ptr.device
+        with self._ctx():
+            if out is None:
+                col = torch.empty(max(total, 1), dtype=torch.int32, device=dev)
+                val = torch.empty(max(total, 1), dtype=self.dtype, device=dev)
+            else:
+                col, val = out
+        cols, vals, o = [], [], 0
+        for z in self.nnz:
+            cols.append(col[o:o + z])
+            vals.append(val[o:o + z])
+            o += z
+        st = reap_spgemm_batch_numeric(self.plan.handle, As, Bs, self._rp_views, cols, vals)
+        if st != REAP_OK:
+            raise SpGEMMError(st, "reap_spgemm_batch_numeric")
+        return [DeviceCSR(A.rows, B.cols, rp, c, v) for A, B, rp, c, v in zip(As, Bs, self._rp_views, cols, vals)]
+
+    def synchronize(self):
+        if self.stream is not None:
+            self.stream.synchronize()
+        else:
+            torch.cuda.synchronize()
+
+    def close(self):
+        self.plan.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class _NullCtx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+def spgemm_batch(As, Bs, dtype=None, c_index_dtype=torch.int32, graph: bool = False, **options):
+    """C_q = A_q * B_q for every q, in one batch; returns the list of results."""
+    dtype = dtype or As[0].dtype
+    with Batch(dtype, c_index_dtype, graph=graph, **options) as b:
+        b.symbolic(As, Bs)
+        out = b.numeric(As, Bs)
+        b.synchronize()
+    return out
 
 
 def spgemm(A: DeviceCSR, B: DeviceCSR, c_index_dtype=None, plan: Plan | None = None, **options) -> DeviceCSR:

@@ -26,6 +26,8 @@ EXPORTED = (
     "reap_spgemm_create",
     "reap_spgemm_symbolic",
     "reap_spgemm_numeric",
+    "reap_spgemm_batch_symbolic",
+    "reap_spgemm_batch_numeric",
     "reap_spgemm_destroy",
     "reap_spgemm_bin_stats",
     "reap_spgemm_phase_times",
@@ -57,7 +59,8 @@ class reap_options_t(ctypes.Structure):
         ("group_lds_values", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("wave_small_values", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -96,6 +99,14 @@ def load():
     lib.reap_spgemm_symbolic.restype = st
     lib.reap_spgemm_numeric.argtypes = [P, ctypes.POINTER(reap_csr_t), ctypes.POINTER(reap_csr_t), P, P, P]
     lib.reap_spgemm_numeric.restype = st
+    PP = ctypes.POINTER(P)
+    lib.reap_spgemm_batch_symbolic.argtypes = [P, ctypes.c_int64, ctypes.POINTER(reap_csr_t),
+                                               ctypes.POINTER(reap_csr_t), PP, ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]
+    lib.reap_spgemm_batch_symbolic.restype = st
+    lib.reap_spgemm_batch_numeric.argtypes = [P, ctypes.c_int64, ctypes.POINTER(reap_csr_t),
+                                              ctypes.POINTER(reap_csr_t), PP, PP, PP]
+    lib.reap_spgemm_batch_numeric.restype = st
     lib.reap_spgemm_destroy.argtypes = [P]
     lib.reap_spgemm_destroy.restype = st
     lib.reap_spgemm_bin_stats.argtypes = [P, ctypes.POINTER(reap_bin_stats_t)]

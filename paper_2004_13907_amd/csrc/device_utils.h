@@ -156,6 +156,17 @@ __device__ __forceinline__ int xcd_contiguous_block(int b, int n) {
     return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Index q of the product that owns workgroup b: start[q] <= b < start[q + 1]
+// (start is non-decreasing, start[0] = 0).  Uniform across the workgroup.
+__device__ __forceinline__ int find_product(const int32_t* start, int nprod, int b) {
+    int lo = 0, hi = nprod;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // Multiplicative hash for LDS open-addressing tables (Knuth's constant).
 __device__ __forceinline__ uint32_t hash_col(int32_t c) { return (uint32_t)c * 2654435761u; }
 

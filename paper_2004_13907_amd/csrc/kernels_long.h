@@ -7,8 +7,9 @@
 // the bitmap words, so that the rank of a column (its position in the sorted
 // row) is one LDS read and a popcount, and adds each product into that slot.
 //
-// Rows are taken from the long-row list with a grid-stride loop (row j goes to
-// workgroup j mod gridDim.x), so every loop bound is known when the row starts.
+// Rows are taken from the batch's long-row list of (product, row) pairs with a
+// grid-stride loop (entry j goes to workgroup j mod gridDim.x), so every loop
+// bound is known when the row starts.
 #pragma once
 #include "device_utils.h"
 #include "kernels_symbolic.h"
@@ -105,17 +106,20 @@ __device__ __forceinline__ long long long_row_count(IdxT rs, int64_t nA, const i
 // long row.  The window is [0, n) when n fits one segment, else the row's
 // [min column, max column] (one extra walk of the products).
 template <typename IdxT>
-__global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p) {
+__global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P,
+                                                          BatchMap bm) {
     __shared__ uint32_t s_bits[kLongSegWords];
     __shared__ LongChunk<IdxT> s_tb[kLongWaves];
     __shared__ long long s_red[kLongWaves];
     __shared__ int s_redi[kLongWaves];
 
     const int w = threadIdx.x / kWave;
-    const int nG = (int)p.ctr->n_group;
-    const int seg_cols = p.th.group_lds_span;
-    for (int j = blockIdx.x; j < nG; j += gridDim.x) {
-        const int64_t i = p.group_rows[j];
+    const int nL = (int)*bm.n_long;
+    for (int j = blockIdx.x; j < nL; j += gridDim.x) {
+        const int2 ent = bm.long_list[j];
+        const SymArgs<IdxT> p = P ? P[ent.x] : p0;
+        const int seg_cols = p.th.group_lds_span;
+        const int64_t i = ent.y;
         const IdxT rs = p.a_rp[i];
         const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
         const long long prods = long_row_count<IdxT>(rs, nA, p.a_col, p.b_rp, s_red);
@@ -175,17 +179,20 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p) {
 // order.  Only this workgroup touches the row's slots during the kernel, so
 // the atomics are workgroup-scoped.
 template <typename T, typename IdxT, typename IdxC>
-__global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC> p) {
+__global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
+                                                          const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm) {
     __shared__ uint32_t s_bits[kLongSegWords];
     __shared__ uint32_t s_pfx[kLongSegWords];
     __shared__ LongChunk<IdxT> s_tb[kLongWaves];
     __shared__ long long s_red[kLongWaves];
 
     const int w = threadIdx.x / kWave;
-    const int nG = (int)p.ctr->n_group;
-    const int seg_cols = p.th.group_lds_span;
-    for (int j = blockIdx.x; j < nG; j += gridDim.x) {
-        const int64_t i = p.group_rows[j];
+    const int nL = (int)*bm.n_long;
+    for (int j = blockIdx.x; j < nL; j += gridDim.x) {
+        const int2 ent = bm.long_list[j];
+        const NumArgs<T, IdxT, IdxC> p = P ? P[ent.x] : p0;
+        const int seg_cols = p.th.group_lds_span;
+        const int64_t i = ent.y;
         const IdxT rs = p.a_rp[i];
         const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
         const int2 wn = p.win[i];

@@ -27,7 +27,6 @@ struct NumArgs {
     T* c_val;
     const uint8_t* cls;
     const int2* win;
-    const int32_t* group_rows;
     Counters* ctr;
     double* gvals;          // per-workgroup FP64 accumulators of long rows with FP32 output
     int64_t gvals_stride;   // doubles per workgroup slot

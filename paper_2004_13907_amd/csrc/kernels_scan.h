@@ -11,30 +11,62 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;  // rows per tile
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t* __restrict__ rnnz, int64_t m,
-                                                             long long* __restrict__ tile_sums) {
+// Per-product view of the scan.
+struct ScanArgs {
+    const int32_t* rnnz;   // [m] nnz of each row of C
+    int64_t m;
+    long long* tiles;      // [ntiles] tile sums, then tile offsets
+    int32_t ntiles;
+    int32_t nparts;
+    const WGPart* parts;   // [nparts] statistics of the wavefront symbolic kernel
+    Counters* ctr;
+    void* c_rp;            // [m + 1] C row pointer (IdxC)
+};
+
+// Tile t of product q: tile_start[q] <= blockIdx.x < tile_start[q + 1].
+struct ScanMap {
+    const int32_t* tile_start;  // [nprod + 1]
+    int32_t nprod;
+};
+
+__device__ __forceinline__ void scan_tile_of(const ScanArgs& s0, const ScanArgs* S, ScanMap sm, ScanArgs& s, int& t) {
+    const int q = sm.nprod > 1 ? find_product(sm.tile_start, sm.nprod, (int)blockIdx.x) : 0;
+    t = (int)blockIdx.x - (sm.nprod > 1 ? sm.tile_start[q] : 0);
+    s = S ? S[q] : s0;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(ScanArgs s0, const ScanArgs* __restrict__ S, ScanMap sm) {
     __shared__ long long s_red[kScanThreads / kWave];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    ScanArgs sa;
+    int t;
+    scan_tile_of(s0, S, sm, sa, t);
+    const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
     long long s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j)
-        if (base + j < m) s += rnnz[base + j];
+        if (base + j < sa.m) s += sa.rnnz[base + j];
     long long total;
     block_excl_scan_i64<kScanThreads>(s, s_red, &total);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+    if (threadIdx.x == 0) sa.tiles[t] = total;
 }
 
-// One workgroup: scans the tile sums in place (exclusive), folds the
-// per-workgroup statistics of the symbolic kernel into the counters, and
-// writes C.row_ptr[m] = nnz(C).
+// One workgroup per product: scans the product's tile sums in place
+// (exclusive), folds the per-workgroup statistics of the symbolic kernel into
+// its counters, and writes C.row_ptr[m] = nnz(C).
 template <typename IdxC>
-__global__ void __launch_bounds__(1024) k_scan_spine(long long* __restrict__ tile_sums, int ntiles,
-                                                     const WGPart* __restrict__ parts, int nparts,
-                                                     Counters* ctr, IdxC* c_rp, int64_t m) {
+__global__ void __launch_bounds__(1024) k_scan_spine(ScanArgs s0, const ScanArgs* __restrict__ S) {
     __shared__ long long s_red[1024 / kWave];
     __shared__ unsigned long long s_prod[1024 / kWave];
     __shared__ unsigned int s_cls[1024 / kWave][kNumClasses];
     __shared__ unsigned int s_max[1024 / kWave][2];
+    const ScanArgs sa = S ? S[blockIdx.x] : s0;
+    long long* __restrict__ tile_sums = sa.tiles;
+    const int ntiles = sa.ntiles;
+    const WGPart* __restrict__ parts = sa.parts;
+    const int nparts = sa.nparts;
+    Counters* ctr = sa.ctr;
+    IdxC* c_rp = static_cast<IdxC*>(sa.c_rp);
+    const int64_t m = sa.m;
     long long carry = 0;
     for (int b0 = 0; b0 < ntiles; b0 += 1024) {
         const int b = b0 + threadIdx.x;
@@ -89,32 +121,37 @@ __global__ void __launch_bounds__(1024) k_scan_spine(long long* __restrict__ til
 }
 
 template <typename IdxC>
-__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int32_t* __restrict__ rnnz, int64_t m,
-                                                             const long long* __restrict__ tile_off,
-                                                             IdxC* __restrict__ c_rp) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(ScanArgs s0, const ScanArgs* __restrict__ S, ScanMap sm) {
     __shared__ long long s_red[kScanThreads / kWave];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    ScanArgs sa;
+    int t;
+    scan_tile_of(s0, S, sm, sa, t);
+    IdxC* __restrict__ c_rp = static_cast<IdxC*>(sa.c_rp);
+    const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     long long s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        v[j] = (base + j < m) ? rnnz[base + j] : 0;
+        v[j] = (base + j < sa.m) ? sa.rnnz[base + j] : 0;
         s += v[j];
     }
     long long total;
-    long long run = tile_off[blockIdx.x] + block_excl_scan_i64<kScanThreads>(s, s_red, &total);
+    long long run = sa.tiles[t] + block_excl_scan_i64<kScanThreads>(s, s_red, &total);
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        if (base + j < m) c_rp[base + j] = (IdxC)run;
+        if (base + j < sa.m) c_rp[base + j] = (IdxC)run;
         run += v[j];
     }
 }
 
 // Zeroes the counters (a kernel rather than a memset, so the sequence can be
 // captured in a graph).
-__global__ void k_zero_counters(Counters* ctr) {
+__global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long) {
     uint32_t* p = reinterpret_cast<uint32_t*>(ctr);
-    for (int x = threadIdx.x; x < (int)(sizeof(Counters) / 4); x += blockDim.x) p[x] = 0u;
+    const int64_t words = (int64_t)nprod * (int64_t)(sizeof(Counters) / 4);
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words; x += (int64_t)gridDim.x * blockDim.x)
+        p[x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_long = 0u;
 }
 
 }  // namespace reap

@@ -18,9 +18,8 @@ struct SymArgs {
     uint8_t* cls;              // [m] row class
     int32_t* rnnz;             // [m] nnz of each row of C
     int2* win;                 // [m] {lo, words} bitmap window of wavefront rows; {lo, span} of long rows
-    int32_t* group_rows;       // [m] list of long rows
-    Counters* ctr;
-    WGPart* parts;             // [gridDim.x] per-workgroup statistics
+    Counters* ctr;             // this product's counters
+    WGPart* parts;             // per-workgroup statistics of the wavefront symbolic kernel
     Thresholds th;
 };
 

@@ -304,8 +304,9 @@ __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan&
 // with more than 64 entries or th.wave_max_products products go to the
 // long-row list.
 template <typename IdxT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_sym_wave(SymArgs<IdxT> p) {
-    constexpr int W = 4;
+__global__ void __launch_bounds__(kWaveKernelWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
+k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
+    constexpr int W = kWaveKernelWaves;
     constexpr int MAXIT = kWaveMaxIt;
     __shared__ uint32_t s_bits[W][padded_words(kWaveBitsWords)];  // padded, + a dummy word
     __shared__ RowTable<IdxT> s_tb[W];
@@ -314,7 +315,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const SymArgs<IdxT> p = P ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     uint32_t* bits = s_bits[w];
     RowTable<IdxT>& tb = s_tb[w];
@@ -371,14 +375,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
         if (cls == kClsGroup) group_flags |= 1u << r;
     }
 
-    // append this wavefront's long rows with one atomic
+    // append this wavefront's long rows to the batch's list with one atomic
     if (group_flags) {
         const bool mine = lane < kRowsPerWave && ((group_flags >> (lane & 31)) & 1u);
-        const uint64_t bm = ballot(mine);
+        const uint64_t lm = ballot(mine);
         int base = 0;
-        if (lane == 0) base = (int)atomicAdd(&p.ctr->n_group, (unsigned)__popcll(bm));
+        if (lane == 0) base = (int)atomicAdd(bm.n_long, (unsigned)__popcll(lm));
         base = shfl(base, 0);
-        if (mine) p.group_rows[base + mbcnt(bm)] = (int32_t)(row0 + lane);
+        if (mine) bm.long_list[base + mbcnt(lm)] = make_int2(q, (int)(row0 + lane));
     }
 
     if (lane == 0) {
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
             t.max_prod = max(t.max_prod, s_part[v].max_prod);
             t.max_nnz = max(t.max_nnz, s_part[v].max_nnz);
         }
-        p.parts[blockIdx.x] = t;
+        p.parts[blk] = t;
     }
 }
 
@@ -476,7 +480,7 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
 // one LDS read plus a popcount.
 template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT, int W>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
-k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
+k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
     __shared__ uint2 s_bp[W][padded_words(WMAX)];  // .x bitmap word, .y set bits before it (padded, + dummy)
     __shared__ double s_vals[W][NCMAX + 1];
     __shared__ int32_t s_cols[W][NCMAX + 1];
@@ -491,7 +495,10 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
     RowTable<IdxT>& tb = s_tb[w];
     WaveStage<IdxT>& st = s_stage[w];
 
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const NumArgs<T, IdxT, IdxC> p = P ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool mine = lane < nrows && p.cls[row0 + lane] == want;
@@ -521,7 +528,8 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
 // the occupied slots are compacted and each entry is placed by counting the
 // smaller columns.
 template <typename T, typename IdxT, typename IdxC, int W>
-__global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC> p, uint8_t want) {
+__global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P,
+                                                          BatchMap bm, uint8_t want) {
     constexpr int MAXIT = kWaveHashIt;
     __shared__ uint32_t s_keys[W][kWaveHashSlots];
     __shared__ double s_hv[W][kWaveHashSlots];
@@ -540,7 +548,10 @@ __global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC>
     WaveStage<IdxT>& st = s_stage[w];
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
-    const int blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const NumArgs<T, IdxT, IdxC> p = P ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool mine = lane < nrows && p.cls[row0 + lane] == want;

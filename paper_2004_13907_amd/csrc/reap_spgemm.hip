@@ -1,5 +1,9 @@
 // Host side of the C ABI declared in include/reap_spgemm.h: plan, workspace,
-// argument checks and kernel launches on the plan's stream.
+// argument checks and kernel launches on the plan's stream.  One engine serves
+// the single-product calls and the batched calls: a batch of N products runs
+// as one launch per kernel (a device table of per-product arguments and a
+// block table map each workgroup to its product), and a single product is the
+// batch of one with its arguments passed by value.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/reap_spgemm.h"
 #include "kernels_long.h"
@@ -28,6 +33,25 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Host record of one product of the last symbolic call.
+struct ProdState {
+    int64_t m = 0, k = 0, n = 0, a_nnz = 0, b_nnz = 0;
+    int32_t blocks = 0;   // workgroups of the wavefront kernels
+    int32_t tiles = 0;    // scan tiles
+    int64_t row_off = 0;  // first row in the per-row workspace arrays
+    int32_t block_off = 0, tile_off = 0;
+    int64_t c_nnz = 0, products = 0;
+};
+
+// Largest argument block of any instantiation (the device tables are sized by it).
+constexpr size_t kArgBytes = std::max({sizeof(SymArgs<int64_t>), sizeof(NumArgs<double, int64_t, int64_t>),
+                                       sizeof(NumArgs<float, int64_t, int64_t>)});
+static_assert(sizeof(SymArgs<int32_t>) <= kArgBytes && sizeof(NumArgs<double, int32_t, int32_t>) <= kArgBytes,
+              "argument table stride");
+
+constexpr int kNumWavesS = kWaveKernelWaves;
+constexpr int kNumWavesH = kWaveKernelWaves;
+
 }  // namespace
 
 struct reap_spgemm_s {
@@ -39,34 +63,57 @@ struct reap_spgemm_s {
     Thresholds th{};
     bool validate = false;
     bool profile = false;
+    bool use_graph = false;   // capture each pass into a HIP graph, replay while the shape repeats
     bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
 
-    Workspace ws;          // per-row arrays, counters, partials
-    Workspace gvals;       // long-row FP64 accumulators (FP32 output only)
-    int64_t ws_rows = -1;  // rows the per-row arrays were carved for
+    Workspace ws;      // counters, per-row arrays, tables
+    Workspace gvals;   // long-row FP64 accumulators (FP32 output only)
+    int64_t cap_rows = -1, cap_prods = 0;
+    int32_t cap_blocks = 0, cap_tiles = 0;
+    uint64_t ws_generation = 0;
 
-    uint8_t* cls = nullptr;
+    Counters* ctr = nullptr;       // [nprod]
+    unsigned int* n_long = nullptr;
+    uint8_t* cls = nullptr;        // per row (all products)
     int32_t* rnnz = nullptr;
     int2* win = nullptr;
-    int32_t* group_rows = nullptr;
-    Counters* ctr = nullptr;
-    WGPart* parts = nullptr;
-    long long* tiles = nullptr;
-    int nparts = 0;
-    int ntiles = 0;
+    int2* long_list = nullptr;
+    WGPart* parts = nullptr;       // per wavefront-kernel workgroup (all products)
+    long long* tiles = nullptr;    // per scan tile (all products)
+    int32_t* blk_start = nullptr;  // [nprod + 1]
+    int32_t* tile_start = nullptr; // [nprod + 1]
+    char* sym_args = nullptr;      // [nprod] SymArgs
+    char* num_args = nullptr;      // [nprod] NumArgs
+    ScanArgs* scan_args = nullptr; // [nprod]
 
-    Counters* h_ctr = nullptr;  // pinned host mirror
+    // pinned host memory: counters mirror (+ long-row count) and argument staging
+    Counters* h_ctr = nullptr;
+    size_t h_ctr_cap = 0;          // products
+    char* h_stage = nullptr;       // symbolic tables
+    char* h_stage_num = nullptr;   // numeric table
+    size_t stage_cap = 0;          // products
+    hipEvent_t ev_num_upload = nullptr;
+    bool num_upload_recorded = false;
 
-    // state of the last symbolic pass
+    // state of the last symbolic call
     bool have_symbolic = false;
-    int64_t m = 0, k = 0, n = 0, a_nnz = 0, b_nnz = 0;
+    int nprod = 0;
+    std::vector<ProdState> prods;
     reap_index_t in_idx = REAP_I32;
-    int64_t c_nnz = 0;
-    int group_grid = 0;
+    int64_t total_rows = 0;
+    int32_t total_blocks = 0, total_tiles = 0;
+    unsigned int long_rows = 0;
+    int long_grid = 1;
     int64_t gvals_stride = 0;
+    Counters agg{};                // summed / maxed over the products (bin statistics)
+
+    // captured passes
+    hipGraphExec_t g_sym = nullptr, g_num = nullptr;
+    std::vector<uint64_t> g_sym_key, g_num_key;
 
     hipEvent_t ev[2 * kNumPhases] = {};
     bool events_ok = false;
+    bool capturing = false;
     bool phase_used[kNumPhases] = {};   // recorded and not yet folded into acc_ms
     double acc_ms[kNumPhases] = {};     // accumulated device time per phase
     long long acc_calls[kNumPhases] = {};
@@ -74,12 +121,7 @@ struct reap_spgemm_s {
 
 namespace {
 
-constexpr int kSymWaves = 4;
-constexpr int kNumWavesS = 4;
-constexpr int kNumWavesH = 4;
-
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
 
 #define REAP_HIP(call)                                   \
     do {                                                 \
@@ -99,8 +141,7 @@ int clampi(int v, int lo, int hi, int dflt) {
     return std::min(std::max(v, lo), hi);
 }
 
-reap_status_t check_csr(const reap_csr_t* M, reap_dtype_t dt) {
-    (void)dt;
+reap_status_t check_csr(const reap_csr_t* M) {
     if (!M) return REAP_ERR_INVALID_ARG;
     if (M->rows < 0 || M->cols < 0 || M->nnz < 0) return REAP_ERR_INVALID_ARG;
     if (M->cols > INT32_MAX) return REAP_ERR_INVALID_ARG;  // int32 column indices
@@ -111,24 +152,72 @@ reap_status_t check_csr(const reap_csr_t* M, reap_dtype_t dt) {
     return REAP_OK;
 }
 
-reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t m) {
-    if (p->ws_rows >= m && p->ws.base) return REAP_OK;
-    const int64_t mm = std::max<int64_t>(m, 1);
-    const int sym_blocks = (int)((mm + kSymWaves * kRowsPerWave - 1) / (kSymWaves * kRowsPerWave));
-    const int ntiles = (int)((mm + kScanTile - 1) / kScanTile);
+void release_graphs(reap_spgemm_s* p) {
+    if (p->g_sym) (void)hipGraphExecDestroy(p->g_sym);
+    if (p->g_num) (void)hipGraphExecDestroy(p->g_num);
+    p->g_sym = p->g_num = nullptr;
+    p->g_sym_key.clear();
+    p->g_num_key.clear();
+}
+
+// Pinned staging and counter mirror for `nprod` products.
+reap_status_t ensure_host(reap_spgemm_s* p, int nprod) {
+    if ((size_t)nprod <= p->stage_cap && p->h_ctr) return REAP_OK;
+    if (p->ev_num_upload && p->num_upload_recorded) (void)hipEventSynchronize(p->ev_num_upload);
+    (void)hipStreamSynchronize(p->stream);
+    release_graphs(p);  // captured copies read the old staging buffers
+    if (p->h_ctr) (void)hipHostFree(p->h_ctr);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
+    p->h_ctr = nullptr;
+    p->h_stage = p->h_stage_num = nullptr;
+    p->stage_cap = 0;
+    const size_t cap = std::max<size_t>((size_t)nprod, 1);
+    const size_t ctr_bytes = (cap + 1) * sizeof(Counters);  // the last slot holds the long-row count
+    const size_t stage_bytes = cap * (kArgBytes + sizeof(ScanArgs)) + 2 * (cap + 1) * sizeof(int32_t) + 256;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->h_ctr), ctr_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&p->h_stage), stage_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&p->h_stage_num), cap * kArgBytes + 256, hipHostMallocDefault) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return REAP_ERR_OUT_OF_MEMORY;
+    }
+    std::memset(p->h_ctr, 0, ctr_bytes);
+    p->stage_cap = cap;
+    p->h_ctr_cap = cap;
+    return REAP_OK;
+}
+
+// Device workspace for the given totals (grows, never shrinks).
+reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, int32_t tiles, int nprod) {
+    if (p->ws.base && rows <= p->cap_rows && blocks <= p->cap_blocks && tiles <= p->cap_tiles &&
+        (int64_t)nprod <= p->cap_prods)
+        return REAP_OK;
+    const int64_t R = std::max<int64_t>({rows, p->cap_rows, 1});
+    const int32_t Bk = std::max({blocks, p->cap_blocks, 1});
+    const int32_t Tl = std::max({tiles, p->cap_tiles, 1});
+    const int64_t Q = std::max<int64_t>({(int64_t)nprod, p->cap_prods, 1});
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t o_ctr = carve(sizeof(Counters));
-    const size_t o_cls = carve((size_t)mm);
-    const size_t o_rnnz = carve((size_t)mm * 4);
-    const size_t o_win = carve((size_t)mm * 8);
-    const size_t o_grp = carve((size_t)mm * 4);
-    const size_t o_parts = carve((size_t)sym_blocks * sizeof(WGPart));
-    const size_t o_tiles = carve((size_t)ntiles * 8);
+    const size_t o_ctr = carve((size_t)Q * sizeof(Counters));
+    const size_t o_nlong = carve(sizeof(unsigned int));
+    const size_t o_cls = carve((size_t)R);
+    const size_t o_rnnz = carve((size_t)R * 4);
+    const size_t o_win = carve((size_t)R * 8);
+    const size_t o_long = carve((size_t)R * 8);
+    const size_t o_parts = carve((size_t)Bk * sizeof(WGPart));
+    const size_t o_tiles = carve((size_t)Tl * 8);
+    const size_t o_bs = carve((size_t)(Q + 1) * 4);
+    const size_t o_ts = carve((size_t)(Q + 1) * 4);
+    const size_t o_sa = carve((size_t)Q * kArgBytes);
+    const size_t o_na = carve((size_t)Q * kArgBytes);
+    const size_t o_sc = carve((size_t)Q * sizeof(ScanArgs));
+    (void)hipStreamSynchronize(p->stream);
+    release_graphs(p);
     if (p->ws.base) {
         (void)hipFree(p->ws.base);
         p->ws.base = nullptr;
@@ -137,27 +226,39 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t m) {
     void* base = nullptr;
     if (hipMalloc(&base, off) != hipSuccess) {
         (void)hipGetLastError();
-        p->ws_rows = -1;
+        p->cap_rows = -1;
+        p->cap_blocks = p->cap_tiles = 0;
+        p->cap_prods = 0;
         return REAP_ERR_OUT_OF_MEMORY;
     }
     char* b = static_cast<char*>(base);
     p->ws.base = base;
     p->ws.bytes = off;
     p->ctr = reinterpret_cast<Counters*>(b + o_ctr);
+    p->n_long = reinterpret_cast<unsigned int*>(b + o_nlong);
     p->cls = reinterpret_cast<uint8_t*>(b + o_cls);
     p->rnnz = reinterpret_cast<int32_t*>(b + o_rnnz);
     p->win = reinterpret_cast<int2*>(b + o_win);
-    p->group_rows = reinterpret_cast<int32_t*>(b + o_grp);
+    p->long_list = reinterpret_cast<int2*>(b + o_long);
     p->parts = reinterpret_cast<WGPart*>(b + o_parts);
     p->tiles = reinterpret_cast<long long*>(b + o_tiles);
-    p->ws_rows = mm;
+    p->blk_start = reinterpret_cast<int32_t*>(b + o_bs);
+    p->tile_start = reinterpret_cast<int32_t*>(b + o_ts);
+    p->sym_args = b + o_sa;
+    p->num_args = b + o_na;
+    p->scan_args = reinterpret_cast<ScanArgs*>(b + o_sc);
+    p->cap_rows = R;
+    p->cap_blocks = Bk;
+    p->cap_tiles = Tl;
+    p->cap_prods = Q;
+    ++p->ws_generation;
     return REAP_OK;
 }
 
 // With REAP_DEBUG_SYNC=1 in the environment every kernel launch is followed by
 // a stream synchronisation and a line on stderr, so a failing kernel is named.
 void debug_step(reap_spgemm_s* p, const char* kernel) {
-    if (!p->debug_sync) return;
+    if (!p->debug_sync || p->capturing) return;
     fprintf(stderr, "[reap] %s launched\n", kernel);
     fflush(stderr);
     const hipError_t e = hipStreamSynchronize(p->stream);
@@ -166,7 +267,7 @@ void debug_step(reap_spgemm_s* p, const char* kernel) {
 }
 
 void ev_record(reap_spgemm_s* p, int phase, bool end) {
-    if (p->profile && p->events_ok) {
+    if (p->profile && p->events_ok && !p->capturing) {
         (void)hipEventRecord(p->ev[2 * phase + (end ? 1 : 0)], p->stream);
         if (end) p->phase_used[phase] = true;
     }
@@ -189,131 +290,431 @@ void fold_events(reap_spgemm_s* p) {
     }
 }
 
-template <typename IdxT>
-reap_status_t run_symbolic(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_t* B, void* c_row_ptr) {
-    const int64_t m = A->rows;
-    SymArgs<IdxT> a;
-    a.m = m;
-    a.n = B->cols;
-    a.a_rp = static_cast<const IdxT*>(A->row_ptr);
-    a.a_col = A->col_idx;
-    a.b_rp = static_cast<const IdxT*>(B->row_ptr);
-    a.b_col = B->col_idx;
-    a.cls = p->cls;
-    a.rnnz = p->rnnz;
-    a.win = p->win;
-    a.group_rows = p->group_rows;
-    a.ctr = p->ctr;
-    a.parts = p->parts;
-    a.th = p->th;
+BatchMap batch_map(const reap_spgemm_s* p) {
+    BatchMap bm;
+    bm.blk_start = p->blk_start;
+    bm.nprod = p->nprod;
+    bm.long_list = p->long_list;
+    bm.n_long = p->n_long;
+    return bm;
+}
 
-    const int sym_blocks = (int)((m + kSymWaves * kRowsPerWave - 1) / (kSymWaves * kRowsPerWave));
-    const int ntiles = (int)((m + kScanTile - 1) / kScanTile);
+// Argument tables go through device memory for batches and captured passes;
+// a single eager product passes its arguments by value.
+bool use_tables(const reap_spgemm_s* p) { return p->nprod > 1 || p->use_graph; }
+
+// Runs `body` (which enqueues work on the plan's stream) eagerly, or captures
+// it once per key into a graph and replays that graph.
+template <typename Body>
+reap_status_t run_pass(reap_spgemm_s* p, hipGraphExec_t& exec, std::vector<uint64_t>& key_store,
+                       const std::vector<uint64_t>& key, Body&& body) {
+    if (!p->use_graph) return body();
+    if (!(exec && key_store == key)) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key_store.clear();
+        REAP_HIP(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        p->capturing = true;
+        const reap_status_t st = body();
+        p->capturing = false;
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->stream, &graph);
+        if (st != REAP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return REAP_ERR_HIP;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            exec = nullptr;
+            return REAP_ERR_HIP;
+        }
+        key_store = key;
+    }
+    REAP_HIP(hipGraphLaunch(exec, p->stream));
+    return REAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Symbolic pass of the current batch (tables already in the staging buffer).
+
+template <typename IdxT>
+reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const ScanArgs& s0) {
+    const bool tab = use_tables(p);
+    const SymArgs<IdxT>* P = tab ? reinterpret_cast<const SymArgs<IdxT>*>(p->sym_args) : nullptr;
+    const ScanArgs* S = tab ? p->scan_args : nullptr;
+    const BatchMap bm = batch_map(p);
+    ScanMap sm;
+    sm.tile_start = p->tile_start;
+    sm.nprod = p->nprod;
+
+    if (tab) {
+        char* h = p->h_stage;
+        // layout in staging: [sym args][scan args][blk_start][tile_start]; copied piecewise
+        REAP_HIP(hipMemcpyAsync(p->sym_args, h, (size_t)p->nprod * kArgBytes, hipMemcpyHostToDevice, p->stream));
+        h += (size_t)p->nprod * kArgBytes;
+        REAP_HIP(hipMemcpyAsync(p->scan_args, h, (size_t)p->nprod * sizeof(ScanArgs), hipMemcpyHostToDevice,
+                                p->stream));
+        h += (size_t)p->nprod * sizeof(ScanArgs);
+        REAP_HIP(hipMemcpyAsync(p->blk_start, h, (size_t)(p->nprod + 1) * 4, hipMemcpyHostToDevice, p->stream));
+        h += (size_t)(p->nprod + 1) * 4;
+        REAP_HIP(hipMemcpyAsync(p->tile_start, h, (size_t)(p->nprod + 1) * 4, hipMemcpyHostToDevice, p->stream));
+    }
+    const int zb = (int)std::min<int64_t>(1024, ((int64_t)p->nprod * (int64_t)(sizeof(Counters) / 4) + 255) / 256);
+    hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, p->nprod, p->n_long);
+    REAP_LAUNCH_CHECK();
 
     ev_record(p, kPhSymbolic, false);
-    if (sym_blocks > 0) {
-        hipLaunchKernelGGL(k_sym_wave<IdxT>, dim3(sym_blocks), dim3(kSymWaves * kWave), 0, p->stream, a);
+    if (p->total_blocks > 0) {
+        hipLaunchKernelGGL(k_sym_wave<IdxT>, dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0, p->stream, a0,
+                           P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
         // the long-row count is known on the device only: a fixed grid walks the list
-        const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)p->num_cus * 2));
-        hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a);
+        const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * 2));
+        hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_long_sym");
     }
     ev_record(p, kPhSymbolic, true);
     ev_record(p, kPhScan, false);
-    if (ntiles > 0) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, p->stream, p->rnnz, m, p->tiles);
+    if (p->total_tiles > 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S, sm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_scan_tiles");
     }
     if (p->cidx == REAP_I32) {
-        hipLaunchKernelGGL(k_scan_spine<int32_t>, dim3(1), dim3(1024), 0, p->stream, p->tiles, ntiles, p->parts,
-                           sym_blocks, p->ctr, static_cast<int32_t*>(c_row_ptr), m);
+        hipLaunchKernelGGL(k_scan_spine<int32_t>, dim3(p->nprod), dim3(1024), 0, p->stream, s0, S);
         REAP_LAUNCH_CHECK();
-        if (ntiles > 0) {
-            hipLaunchKernelGGL(k_scan_apply<int32_t>, dim3(ntiles), dim3(kScanThreads), 0, p->stream, p->rnnz, m,
-                               p->tiles, static_cast<int32_t*>(c_row_ptr));
+        if (p->total_tiles > 0) {
+            hipLaunchKernelGGL(k_scan_apply<int32_t>, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S,
+                               sm);
             REAP_LAUNCH_CHECK();
         }
     } else {
-        hipLaunchKernelGGL(k_scan_spine<int64_t>, dim3(1), dim3(1024), 0, p->stream, p->tiles, ntiles, p->parts,
-                           sym_blocks, p->ctr, static_cast<int64_t*>(c_row_ptr), m);
+        hipLaunchKernelGGL(k_scan_spine<int64_t>, dim3(p->nprod), dim3(1024), 0, p->stream, s0, S);
         REAP_LAUNCH_CHECK();
-        if (ntiles > 0) {
-            hipLaunchKernelGGL(k_scan_apply<int64_t>, dim3(ntiles), dim3(kScanThreads), 0, p->stream, p->rnnz, m,
-                               p->tiles, static_cast<int64_t*>(c_row_ptr));
+        if (p->total_tiles > 0) {
+            hipLaunchKernelGGL(k_scan_apply<int64_t>, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S,
+                               sm);
             REAP_LAUNCH_CHECK();
         }
     }
+    debug_step(p, "k_scan");
     ev_record(p, kPhScan, true);
+    // counters of every product, then the long-row count, to the host
+    REAP_HIP(hipMemcpyAsync(p->h_ctr, p->ctr, (size_t)p->nprod * sizeof(Counters), hipMemcpyDeviceToHost, p->stream));
+    REAP_HIP(hipMemcpyAsync(reinterpret_cast<char*>(p->h_ctr) + (size_t)p->h_ctr_cap * sizeof(Counters), p->n_long,
+                            sizeof(unsigned int), hipMemcpyDeviceToHost, p->stream));
     return REAP_OK;
 }
 
 template <typename IdxT>
-reap_status_t run_validate(reap_spgemm_s* p, const reap_csr_t* M, unsigned bit) {
+reap_status_t run_validate(reap_spgemm_s* p, const reap_csr_t* M, Counters* ctr, unsigned bit) {
     const int64_t n = M->rows + 1;
     const int blocks = (int)((n + 255) / 256);
     hipLaunchKernelGGL(k_validate<IdxT>, dim3(blocks), dim3(256), 0, p->stream, static_cast<const IdxT*>(M->row_ptr),
-                       M->col_idx, M->rows, M->cols, M->nnz, p->ctr, bit);
+                       M->col_idx, M->rows, M->cols, M->nnz, ctr, bit);
     REAP_LAUNCH_CHECK();
     return REAP_OK;
 }
 
-template <typename T, typename IdxT, typename IdxC>
-reap_status_t run_numeric(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_t* B, const void* c_row_ptr,
-                          int32_t* c_col, void* c_val) {
-    NumArgs<T, IdxT, IdxC> a;
-    a.m = A->rows;
-    a.n = B->cols;
-    a.a_rp = static_cast<const IdxT*>(A->row_ptr);
-    a.a_col = A->col_idx;
-    a.a_val = static_cast<const T*>(A->values);
-    a.b_rp = static_cast<const IdxT*>(B->row_ptr);
-    a.b_col = B->col_idx;
-    a.b_val = static_cast<const T*>(B->values);
-    a.c_rp = static_cast<const IdxC*>(c_row_ptr);
-    a.c_col = c_col;
-    a.c_val = static_cast<T*>(c_val);
-    a.cls = p->cls;
-    a.win = p->win;
-    a.group_rows = p->group_rows;
-    a.ctr = p->ctr;
-    a.gvals = static_cast<double*>(p->gvals.base);
-    a.gvals_stride = p->gvals_stride;
-    a.th = p->th;
-    const int64_t m = A->rows;
-    const Counters& h = *p->h_ctr;
+template <typename IdxT>
+reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_t* B, void* const* c_row_ptr) {
+    const int nprod = p->nprod;
+    // argument tables in the staging buffer
+    char* h = p->h_stage;
+    SymArgs<IdxT> a0{};
+    ScanArgs s0{};
+    for (int q = 0; q < nprod; ++q) {
+        const ProdState& ps = p->prods[q];
+        SymArgs<IdxT> a{};
+        a.m = ps.m;
+        a.n = ps.n;
+        a.a_rp = static_cast<const IdxT*>(A[q].row_ptr);
+        a.a_col = A[q].col_idx;
+        a.b_rp = static_cast<const IdxT*>(B[q].row_ptr);
+        a.b_col = B[q].col_idx;
+        a.cls = p->cls + ps.row_off;
+        a.rnnz = p->rnnz + ps.row_off;
+        a.win = p->win + ps.row_off;
+        a.ctr = p->ctr + q;
+        a.parts = p->parts + ps.block_off;
+        a.th = p->th;
+        ScanArgs s{};
+        s.rnnz = p->rnnz + ps.row_off;
+        s.m = ps.m;
+        s.tiles = p->tiles + ps.tile_off;
+        s.ntiles = ps.tiles;
+        s.nparts = ps.blocks;
+        s.parts = p->parts + ps.block_off;
+        s.ctr = p->ctr + q;
+        s.c_rp = c_row_ptr[q];
+        // the kernels index the table as an array of this instantiation's type
+        std::memcpy(h + (size_t)q * sizeof(a), &a, sizeof(a));
+        std::memcpy(h + (size_t)nprod * kArgBytes + (size_t)q * sizeof(ScanArgs), &s, sizeof(s));
+        if (q == 0) {
+            a0 = a;
+            s0 = s;
+        }
+    }
+    int32_t* bs = reinterpret_cast<int32_t*>(h + (size_t)nprod * (kArgBytes + sizeof(ScanArgs)));
+    int32_t* ts = bs + nprod + 1;
+    for (int q = 0; q < nprod; ++q) {
+        bs[q] = p->prods[q].block_off;
+        ts[q] = p->prods[q].tile_off;
+    }
+    bs[nprod] = p->total_blocks;
+    ts[nprod] = p->total_tiles;
 
+    if (p->validate) {
+        const int zb = (int)std::min<int64_t>(1024, ((int64_t)nprod * (int64_t)(sizeof(Counters) / 4) + 255) / 256);
+        hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, nprod, p->n_long);
+        REAP_LAUNCH_CHECK();
+        reap_status_t st;
+        for (int q = 0; q < nprod; ++q) {
+            if ((st = run_validate<IdxT>(p, &A[q], p->ctr + q, 1u)) != REAP_OK) return st;
+            if ((st = run_validate<IdxT>(p, &B[q], p->ctr + q, 2u)) != REAP_OK) return st;
+        }
+        REAP_HIP(hipMemcpyAsync(p->h_ctr, p->ctr, (size_t)nprod * sizeof(Counters), hipMemcpyDeviceToHost, p->stream));
+        REAP_HIP(hipStreamSynchronize(p->stream));
+        for (int q = 0; q < nprod; ++q)
+            if (p->h_ctr[q].bad_csr) return REAP_ERR_BAD_CSR;
+    }
+
+    std::vector<uint64_t> key = {p->ws_generation, (uint64_t)nprod, (uint64_t)p->total_blocks,
+                                 (uint64_t)p->total_tiles, (uint64_t)p->total_rows, (uint64_t)p->cidx,
+                                 (uint64_t)sizeof(IdxT)};
+    return run_pass(p, p->g_sym, p->g_sym_key, key, [&]() { return launch_symbolic<IdxT>(p, a0, s0); });
+}
+
+reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                             void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes) {
+    if (!p || count < 1 || count > INT32_MAX / 2 || !A || !B || !c_row_ptr || !c_nnz) return REAP_ERR_INVALID_ARG;
+    reap_status_t st;
+    const reap_index_t in_idx = A[0].row_ptr_type;
+    int64_t rows = 0, blocks = 0, tiles = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        if ((st = check_csr(&A[q])) != REAP_OK) return st;
+        if ((st = check_csr(&B[q])) != REAP_OK) return st;
+        if (A[q].cols != B[q].rows) return REAP_ERR_INVALID_ARG;
+        if (A[q].row_ptr_type != in_idx || B[q].row_ptr_type != in_idx) return REAP_ERR_INVALID_ARG;
+        if (A[q].rows > INT32_MAX - 1) return REAP_ERR_INVALID_ARG;  // row ids are stored as int32
+        if (!c_row_ptr[q]) return REAP_ERR_INVALID_ARG;
+        rows += A[q].rows;
+        blocks += (A[q].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+        tiles += (A[q].rows + kScanTile - 1) / kScanTile;
+    }
+    if (rows > INT32_MAX || blocks > INT32_MAX || tiles > INT32_MAX) return REAP_ERR_INVALID_ARG;
+    p->have_symbolic = false;
+    if (p->ev_num_upload && p->num_upload_recorded) (void)hipEventSynchronize(p->ev_num_upload);
+    if ((st = ensure_host(p, (int)count)) != REAP_OK) return st;
+    if ((st = ensure_workspace(p, rows, (int32_t)blocks, (int32_t)tiles, (int)count)) != REAP_OK) return st;
+
+    p->nprod = (int)count;
+    p->prods.assign((size_t)count, ProdState{});
+    p->in_idx = in_idx;
+    int64_t ro = 0;
+    int32_t bo = 0, to = 0;
+    for (int64_t q = 0; q < count; ++q) {
+        ProdState& ps = p->prods[(size_t)q];
+        ps.m = A[q].rows;
+        ps.k = A[q].cols;
+        ps.n = B[q].cols;
+        ps.a_nnz = A[q].nnz;
+        ps.b_nnz = B[q].nnz;
+        ps.blocks = (int32_t)((ps.m + kRowsPerBlock - 1) / kRowsPerBlock);
+        ps.tiles = (int32_t)((ps.m + kScanTile - 1) / kScanTile);
+        ps.row_off = ro;
+        ps.block_off = bo;
+        ps.tile_off = to;
+        ro += ps.m;
+        bo += ps.blocks;
+        to += ps.tiles;
+    }
+    p->total_rows = ro;
+    p->total_blocks = bo;
+    p->total_tiles = to;
+
+    st = (in_idx == REAP_I32) ? symbolic_typed<int32_t>(p, A, B, c_row_ptr)
+                              : symbolic_typed<int64_t>(p, A, B, c_row_ptr);
+    if (st != REAP_OK) return st;
+    REAP_HIP(hipStreamSynchronize(p->stream));
+    fold_events(p);  // this call's symbolic phases and the previous numeric call's phases
+
+    const unsigned int nl =
+        *reinterpret_cast<const unsigned int*>(reinterpret_cast<const char*>(p->h_ctr) + p->h_ctr_cap * sizeof(Counters));
+    p->long_rows = nl;
+    p->agg = Counters{};
+    unsigned int max_group_nnz = 0;
+    bool overflow = false;
+    for (int q = 0; q < p->nprod; ++q) {
+        const Counters& h = p->h_ctr[q];
+        ProdState& ps = p->prods[(size_t)q];
+        ps.c_nnz = (int64_t)h.nnz;
+        ps.products = (int64_t)h.products;
+        c_nnz[q] = ps.c_nnz;
+        if (n_products) n_products[q] = ps.products;
+        if (p->cidx == REAP_I32 && ps.c_nnz > INT32_MAX) overflow = true;
+        p->agg.products += h.products;
+        p->agg.nnz += h.nnz;
+        for (int c = 0; c < kNumClasses; ++c) p->agg.cls[c] += h.cls[c];
+        p->agg.max_prod = std::max(p->agg.max_prod, h.max_prod);
+        p->agg.max_nnz = std::max(p->agg.max_nnz, h.max_nnz);
+        max_group_nnz = std::max(max_group_nnz, h.max_group_nnz);
+    }
+
+    // long rows: the list is walked by up to two workgroups per CU; FP32 output
+    // needs an FP64 accumulator per workgroup (one segment of the widest row)
+    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus * 2));
+    p->gvals_stride = 0;
+    if (p->dtype == REAP_F32 && nl > 0) {
+        const int64_t stride =
+            std::max<int64_t>(1, std::min<int64_t>((int64_t)max_group_nnz, (int64_t)p->th.group_lds_span));
+        const size_t need = (size_t)stride * (size_t)p->long_grid * sizeof(double);
+        if (need > p->gvals.bytes) {
+            (void)hipStreamSynchronize(p->stream);
+            if (p->g_num) {
+                (void)hipGraphExecDestroy(p->g_num);
+                p->g_num = nullptr;
+                p->g_num_key.clear();
+            }
+            if (p->gvals.base) (void)hipFree(p->gvals.base);
+            p->gvals.base = nullptr;
+            p->gvals.bytes = 0;
+            if (hipMalloc(&p->gvals.base, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return REAP_ERR_OUT_OF_MEMORY;
+            }
+            p->gvals.bytes = need;
+        }
+        p->gvals_stride = stride;
+    }
+    if (workspace_bytes) *workspace_bytes = p->ws.bytes + p->gvals.bytes;
+    if (overflow) return REAP_ERR_INDEX_OVERFLOW;
+    p->have_symbolic = true;
+    return REAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Numeric pass.
+
+template <typename T, typename IdxT, typename IdxC>
+reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0) {
+    const bool tab = use_tables(p);
+    const NumArgs<T, IdxT, IdxC>* P = tab ? reinterpret_cast<const NumArgs<T, IdxT, IdxC>*>(p->num_args) : nullptr;
+    const BatchMap bm = batch_map(p);
+    if (tab) {
+        REAP_HIP(hipMemcpyAsync(p->num_args, p->h_stage_num, (size_t)p->nprod * kArgBytes, hipMemcpyHostToDevice,
+                                p->stream));
+        if (!p->capturing) {
+            REAP_HIP(hipEventRecord(p->ev_num_upload, p->stream));
+            p->num_upload_recorded = true;
+        }
+    }
     ev_record(p, kPhNumAll, false);
     ev_record(p, kPhNumWave, false);
-    if (h.cls[kClsWaveBmpS] > 0) {
-        const int blocks = (int)((m + kNumWavesS * kRowsPerWave - 1) / (kNumWavesS * kRowsPerWave));
-        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS>), dim3(blocks),
-                           dim3(kNumWavesS * kWave), 0, p->stream, a, (uint8_t)kClsWaveBmpS);
+    if (p->agg.cls[kClsWaveBmpS] > 0) {
+        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS>),
+                           dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm,
+                           (uint8_t)kClsWaveBmpS);
         REAP_LAUNCH_CHECK();
-        debug_step(p, "k_num_wave_bmp (small)");
+        debug_step(p, "k_num_wave_bmp");
     }
     ev_record(p, kPhNumWave, true);
     ev_record(p, kPhNumHash, false);
-    if (h.cls[kClsWaveHash] > 0) {
-        const int blocks = (int)((m + kNumWavesH * kRowsPerWave - 1) / (kNumWavesH * kRowsPerWave));
-        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH>), dim3(blocks), dim3(kNumWavesH * kWave), 0,
-                           p->stream, a, (uint8_t)kClsWaveHash);
+    if (p->agg.cls[kClsWaveHash] > 0) {
+        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH>), dim3(p->total_blocks),
+                           dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_hash");
     }
     ev_record(p, kPhNumHash, true);
     ev_record(p, kPhNumGroup, false);
-    if (h.n_group > 0) {
-        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->group_grid), dim3(kLongThreads), 0, p->stream, a);
+    if (p->long_rows > 0) {
+        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->long_grid), dim3(kLongThreads), 0, p->stream, a0, P,
+                           bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_long_num");
     }
     ev_record(p, kPhNumGroup, true);
     ev_record(p, kPhNumAll, true);
     return REAP_OK;
+}
+
+template <typename T, typename IdxT, typename IdxC>
+reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_csr_t* B, const void* const* c_row_ptr,
+                            int32_t* const* c_col, void* const* c_val) {
+    if (p->ev_num_upload && p->num_upload_recorded) REAP_HIP(hipEventSynchronize(p->ev_num_upload));
+    NumArgs<T, IdxT, IdxC> a0{};
+    for (int q = 0; q < p->nprod; ++q) {
+        const ProdState& ps = p->prods[(size_t)q];
+        NumArgs<T, IdxT, IdxC> a{};
+        a.m = ps.m;
+        a.n = ps.n;
+        a.a_rp = static_cast<const IdxT*>(A[q].row_ptr);
+        a.a_col = A[q].col_idx;
+        a.a_val = static_cast<const T*>(A[q].values);
+        a.b_rp = static_cast<const IdxT*>(B[q].row_ptr);
+        a.b_col = B[q].col_idx;
+        a.b_val = static_cast<const T*>(B[q].values);
+        a.c_rp = static_cast<const IdxC*>(c_row_ptr[q]);
+        a.c_col = c_col[q];
+        a.c_val = static_cast<T*>(c_val[q]);
+        a.cls = p->cls + ps.row_off;
+        a.win = p->win + ps.row_off;
+        a.ctr = p->ctr + q;
+        a.gvals = static_cast<double*>(p->gvals.base);
+        a.gvals_stride = p->gvals_stride;
+        a.th = p->th;
+        std::memcpy(p->h_stage_num + (size_t)q * sizeof(a), &a, sizeof(a));
+        if (q == 0) a0 = a;
+    }
+    std::vector<uint64_t> key = {p->ws_generation, (uint64_t)p->nprod, (uint64_t)p->total_blocks,
+                                 (uint64_t)p->long_rows, (uint64_t)p->long_grid,
+                                 (uint64_t)(p->agg.cls[kClsWaveBmpS] > 0), (uint64_t)(p->agg.cls[kClsWaveHash] > 0),
+                                 (uint64_t)sizeof(T), (uint64_t)sizeof(IdxT), (uint64_t)sizeof(IdxC),
+                                 (uint64_t)(uintptr_t)p->gvals.base, (uint64_t)p->gvals_stride};
+    const reap_status_t st =
+        run_pass(p, p->g_num, p->g_num_key, key, [&]() { return launch_numeric<T, IdxT, IdxC>(p, a0); });
+    if (st == REAP_OK && p->use_graph) {
+        // a replayed graph reads the staging buffer when it runs: keep it until then
+        REAP_HIP(hipEventRecord(p->ev_num_upload, p->stream));
+        p->num_upload_recorded = true;
+    }
+    return st;
+}
+
+reap_status_t numeric_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                            const void* const* c_row_ptr, int32_t* const* c_col, void* const* c_val) {
+    if (!p || !A || !B || !c_row_ptr || !c_col || !c_val) return REAP_ERR_INVALID_ARG;
+    if (!p->have_symbolic || count != p->nprod) return REAP_ERR_STATE;
+    reap_status_t st;
+    int64_t total_nnz = 0;
+    for (int q = 0; q < p->nprod; ++q) {
+        const ProdState& ps = p->prods[(size_t)q];
+        if ((st = check_csr(&A[q])) != REAP_OK) return st;
+        if ((st = check_csr(&B[q])) != REAP_OK) return st;
+        if (!c_row_ptr[q]) return REAP_ERR_INVALID_ARG;
+        if (A[q].rows != ps.m || A[q].cols != ps.k || B[q].cols != ps.n || A[q].nnz != ps.a_nnz ||
+            B[q].nnz != ps.b_nnz || A[q].row_ptr_type != p->in_idx || B[q].row_ptr_type != p->in_idx)
+            return REAP_ERR_STATE;
+        if (ps.c_nnz > 0 && (!c_col[q] || !c_val[q])) return REAP_ERR_INVALID_ARG;
+        total_nnz += ps.c_nnz;
+    }
+    if (total_nnz == 0) return REAP_OK;
+    const bool i32 = p->in_idx == REAP_I32, c32 = p->cidx == REAP_I32;
+    if (p->dtype == REAP_F64) {
+        if (i32 && c32) return numeric_typed<double, int32_t, int32_t>(p, A, B, c_row_ptr, c_col, c_val);
+        if (i32 && !c32) return numeric_typed<double, int32_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
+        if (!i32 && c32) return numeric_typed<double, int64_t, int32_t>(p, A, B, c_row_ptr, c_col, c_val);
+        return numeric_typed<double, int64_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
+    }
+    if (i32 && c32) return numeric_typed<float, int32_t, int32_t>(p, A, B, c_row_ptr, c_col, c_val);
+    if (i32 && !c32) return numeric_typed<float, int32_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
+    if (!i32 && c32) return numeric_typed<float, int64_t, int32_t>(p, A, B, c_row_ptr, c_col, c_val);
+    return numeric_typed<float, int64_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
 }
 
 }  // namespace
@@ -333,7 +734,7 @@ const char* reap_status_string(reap_status_t s) {
     return "unknown status";
 }
 
-const char* reap_version(void) { return "0.1.0"; }
+const char* reap_version(void) { return "0.2.0"; }
 
 reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_index_t c_row_ptr_type, void* stream,
                                  const reap_options_t* opts) {
@@ -341,18 +742,21 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     *plan = nullptr;
     if (dtype != REAP_F32 && dtype != REAP_F64) return REAP_ERR_INVALID_ARG;
     if (c_row_ptr_type != REAP_I32 && c_row_ptr_type != REAP_I64) return REAP_ERR_INVALID_ARG;
+    reap_options_t o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.graph && !stream) return REAP_ERR_INVALID_ARG;  // the legacy default stream cannot be captured
     reap_spgemm_s* p = new (std::nothrow) reap_spgemm_s();
     if (!p) return REAP_ERR_OUT_OF_MEMORY;
     p->dtype = dtype;
     p->cidx = c_row_ptr_type;
     p->stream = static_cast<hipStream_t>(stream);
-    reap_options_t o;
-    std::memset(&o, 0, sizeof(o));
-    if (opts) o = *opts;
     p->validate = o.validate != 0;
     p->profile = o.profile != 0;
+    p->use_graph = o.graph != 0 && !p->validate;
     const char* dbg = std::getenv("REAP_DEBUG_SYNC");
     p->debug_sync = dbg && dbg[0] == '1';
+    if (p->debug_sync) p->use_graph = false;
     p->th.wave_max_products = clampi(o.wave_max_products, 0, kWaveMaxProducts, kWaveMaxProducts);
     p->th.wave_max_span = clampi(o.wave_max_span, 0, 32 * kWaveBitsWords, 32 * kWaveBitsWords);
     p->th.wave_hash_products = clampi(o.wave_hash_products, 0, kWaveHashProducts, kWaveHashProducts);
@@ -361,13 +765,17 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&p->h_ctr), sizeof(Counters), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_num_upload, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete p;
         return REAP_ERR_HIP;
     }
-    std::memset(p->h_ctr, 0, sizeof(Counters));
+    if (ensure_host(p, 1) != REAP_OK) {
+        (void)hipEventDestroy(p->ev_num_upload);
+        delete p;
+        return REAP_ERR_OUT_OF_MEMORY;
+    }
     if (p->profile) {
         p->events_ok = true;
         for (int i = 0; i < 2 * kNumPhases; ++i)
@@ -380,9 +788,13 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
 reap_status_t reap_spgemm_destroy(reap_spgemm_t p) {
     if (!p) return REAP_OK;
     (void)hipStreamSynchronize(p->stream);
+    release_graphs(p);
     if (p->ws.base) (void)hipFree(p->ws.base);
     if (p->gvals.base) (void)hipFree(p->gvals.base);
     if (p->h_ctr) (void)hipHostFree(p->h_ctr);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
+    if (p->ev_num_upload) (void)hipEventDestroy(p->ev_num_upload);
     for (int i = 0; i < 2 * kNumPhases; ++i)
         if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     delete p;
@@ -391,108 +803,37 @@ reap_status_t reap_spgemm_destroy(reap_spgemm_t p) {
 
 reap_status_t reap_spgemm_symbolic(reap_spgemm_t p, const reap_csr_t* A, const reap_csr_t* B, void* c_row_ptr,
                                    int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes) {
-    if (!p || !c_nnz || !c_row_ptr) return REAP_ERR_INVALID_ARG;
-    reap_status_t st;
-    if ((st = check_csr(A, p->dtype)) != REAP_OK) return st;
-    if ((st = check_csr(B, p->dtype)) != REAP_OK) return st;
-    if (A->cols != B->rows) return REAP_ERR_INVALID_ARG;
-    if (A->row_ptr_type != B->row_ptr_type) return REAP_ERR_INVALID_ARG;
-    if (A->rows > INT32_MAX - 1) return REAP_ERR_INVALID_ARG;  // row ids are stored as int32
-    p->have_symbolic = false;
-
-    if ((st = ensure_workspace(p, A->rows)) != REAP_OK) return st;
-    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, p->stream, p->ctr);
-    REAP_LAUNCH_CHECK();
-
-    if (p->validate) {
-        if (A->row_ptr_type == REAP_I32) {
-            if ((st = run_validate<int32_t>(p, A, 1u)) != REAP_OK) return st;
-            if ((st = run_validate<int32_t>(p, B, 2u)) != REAP_OK) return st;
-        } else {
-            if ((st = run_validate<int64_t>(p, A, 1u)) != REAP_OK) return st;
-            if ((st = run_validate<int64_t>(p, B, 2u)) != REAP_OK) return st;
-        }
-        REAP_HIP(hipMemcpyAsync(p->h_ctr, p->ctr, sizeof(Counters), hipMemcpyDeviceToHost, p->stream));
-        REAP_HIP(hipStreamSynchronize(p->stream));
-        if (p->h_ctr->bad_csr) return REAP_ERR_BAD_CSR;
-    }
-
-    st = (A->row_ptr_type == REAP_I32) ? run_symbolic<int32_t>(p, A, B, c_row_ptr)
-                                       : run_symbolic<int64_t>(p, A, B, c_row_ptr);
-    if (st != REAP_OK) return st;
-    REAP_HIP(hipMemcpyAsync(p->h_ctr, p->ctr, sizeof(Counters), hipMemcpyDeviceToHost, p->stream));
-    REAP_HIP(hipStreamSynchronize(p->stream));
-    fold_events(p);  // this call's symbolic phases and the previous numeric call's phases
-    const Counters& h = *p->h_ctr;
-    const int64_t nnz = (int64_t)h.nnz;
-
-    // long rows: one workgroup per list entry up to two per CU; FP32 output
-    // needs an FP64 accumulator per workgroup (one segment of the widest row)
-    p->group_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h.n_group, (int64_t)p->num_cus * 2));
-    p->gvals_stride = 0;
-    if (p->dtype == REAP_F32 && h.n_group > 0) {
-        const int64_t stride =
-            std::max<int64_t>(1, std::min<int64_t>((int64_t)h.max_group_nnz, (int64_t)p->th.group_lds_span));
-        const size_t need = (size_t)stride * (size_t)p->group_grid * sizeof(double);
-        if (need > p->gvals.bytes) {
-            if (p->gvals.base) (void)hipFree(p->gvals.base);
-            p->gvals.base = nullptr;
-            p->gvals.bytes = 0;
-            if (hipMalloc(&p->gvals.base, need) != hipSuccess) {
-                (void)hipGetLastError();
-                return REAP_ERR_OUT_OF_MEMORY;
-            }
-            p->gvals.bytes = need;
-        }
-        p->gvals_stride = stride;
-    }
-
-    *c_nnz = nnz;
-    if (n_products) *n_products = (int64_t)h.products;
-    if (workspace_bytes) *workspace_bytes = p->ws.bytes + p->gvals.bytes;
-    if (p->cidx == REAP_I32 && nnz > INT32_MAX) return REAP_ERR_INDEX_OVERFLOW;
-
-    p->have_symbolic = true;
-    p->m = A->rows;
-    p->k = A->cols;
-    p->n = B->cols;
-    p->a_nnz = A->nnz;
-    p->b_nnz = B->nnz;
-    p->in_idx = A->row_ptr_type;
-    p->c_nnz = nnz;
-    return REAP_OK;
+    if (!p || !A || !B || !c_nnz || !c_row_ptr) return REAP_ERR_INVALID_ARG;
+    void* rp[1] = {c_row_ptr};
+    return symbolic_batch(p, 1, A, B, rp, c_nnz, n_products, workspace_bytes);
 }
 
 reap_status_t reap_spgemm_numeric(reap_spgemm_t p, const reap_csr_t* A, const reap_csr_t* B, const void* c_row_ptr,
                                   int32_t* c_col_idx, void* c_values) {
-    if (!p) return REAP_ERR_INVALID_ARG;
-    reap_status_t st;
-    if ((st = check_csr(A, p->dtype)) != REAP_OK) return st;
-    if ((st = check_csr(B, p->dtype)) != REAP_OK) return st;
-    if (!c_row_ptr) return REAP_ERR_INVALID_ARG;
-    if (!p->have_symbolic) return REAP_ERR_STATE;
-    if (A->rows != p->m || A->cols != p->k || B->cols != p->n || A->nnz != p->a_nnz || B->nnz != p->b_nnz ||
-        A->row_ptr_type != p->in_idx || B->row_ptr_type != p->in_idx)
-        return REAP_ERR_STATE;
-    if (p->c_nnz > 0 && (!c_col_idx || !c_values)) return REAP_ERR_INVALID_ARG;
-    if (p->c_nnz == 0) return REAP_OK;
-    const bool i32 = p->in_idx == REAP_I32, c32 = p->cidx == REAP_I32;
-    if (p->dtype == REAP_F64) {
-        if (i32 && c32) return run_numeric<double, int32_t, int32_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-        if (i32 && !c32) return run_numeric<double, int32_t, int64_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-        if (!i32 && c32) return run_numeric<double, int64_t, int32_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-        return run_numeric<double, int64_t, int64_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-    }
-    if (i32 && c32) return run_numeric<float, int32_t, int32_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-    if (i32 && !c32) return run_numeric<float, int32_t, int64_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-    if (!i32 && c32) return run_numeric<float, int64_t, int32_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
-    return run_numeric<float, int64_t, int64_t>(p, A, B, c_row_ptr, c_col_idx, c_values);
+    if (!p || !A || !B || !c_row_ptr) return REAP_ERR_INVALID_ARG;
+    if (p->have_symbolic && p->nprod != 1) return REAP_ERR_STATE;
+    const void* rp[1] = {c_row_ptr};
+    int32_t* cc[1] = {c_col_idx};
+    void* cv[1] = {c_values};
+    return numeric_batch(p, 1, A, B, rp, cc, cv);
+}
+
+reap_status_t reap_spgemm_batch_symbolic(reap_spgemm_t p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                                         void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products,
+                                         size_t* workspace_bytes) {
+    return symbolic_batch(p, count, A, B, c_row_ptr, c_nnz, n_products, workspace_bytes);
+}
+
+reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                                        const void* const* c_row_ptr, int32_t* const* c_col_idx,
+                                        void* const* c_values) {
+    return numeric_batch(p, count, A, B, c_row_ptr, c_col_idx, c_values);
 }
 
 reap_status_t reap_spgemm_bin_stats(reap_spgemm_t p, reap_bin_stats_t* out) {
     if (!p || !out) return REAP_ERR_INVALID_ARG;
     if (!p->have_symbolic) return REAP_ERR_STATE;
-    const Counters& h = *p->h_ctr;
+    const Counters& h = p->agg;
     out->empty = (int64_t)h.cls[kClsEmpty];
     out->wave_bitmap = (int64_t)(h.cls[kClsWaveBmpS] + h.cls[kClsWaveBmpL]);
     out->wave_hash = (int64_t)h.cls[kClsWaveHash];

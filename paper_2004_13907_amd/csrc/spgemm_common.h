@@ -1,5 +1,6 @@
 // Types shared by the SpGEMM kernels and the host plan.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace reap {
@@ -51,6 +52,22 @@ struct Counters {
     unsigned int max_group_nnz;    // max nnz of a long row
     unsigned int bad_csr;          // validation flags (bit 0: A, bit 1: B)
     unsigned int pad[5];
+};
+
+// Rows handled by one workgroup of the wavefront kernels (4 wavefronts of
+// kRowsPerWave rows); the batch's block table is built for this many rows.
+constexpr int kWaveKernelWaves = 4;
+constexpr int kRowsPerBlock = kWaveKernelWaves * kRowsPerWave;
+
+// Several independent products in one launch.  Workgroup b of a wavefront
+// kernel serves product q with blk_start[q] <= b < blk_start[q + 1]; its
+// arguments are args[q] (or the kernel's by-value argument when nprod == 1).
+// Long rows of every product are appended to one list of (product, row).
+struct BatchMap {
+    const int32_t* blk_start;  // [nprod + 1]
+    int32_t nprod;
+    int2* long_list;           // [sum of rows]
+    unsigned int* n_long;      // length of long_list
 };
 
 // Thresholds of one plan (clamped to the kernel capacities above).

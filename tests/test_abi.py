@@ -43,7 +43,7 @@ def test_status_strings(lib):
     for s in range(7):
         assert lib.reap_status_string(s)
     assert lib.reap_status_string(99) == b"unknown status"
-    assert lib.reap_version() == b"0.1.0"
+    assert lib.reap_version() == b"0.2.0"
 
 
 def test_null_arguments_rejected_without_gpu(lib):

@@ -195,6 +195,35 @@ def test_repeat_pattern_identical(reap):
             assert np.max(np.abs(val.astype(np.float64) - first[2])) <= 1e-5 * np.max(np.abs(first[2]))
 
 
+# --- symbolic-plan reuse: numeric-only re-multiply with new values ------------
+
+@pytest.mark.parametrize("case", ["stencil", "uniform_random_f32"])
+def test_plan_reuse_new_values(reap, case):
+    """One symbolic pass, then numeric passes over operands with the same
+    patterns and fresh values (the re-multiply of an iterative method): every
+    result against the oracle on those values."""
+    if case == "stencil":
+        A = synth.stencil27(9)
+        tdt, npdt = torch.float64, np.float64
+    else:
+        A = synth.erdos_renyi(1500, 1500, 0.02, seed=61, dtype=np.float32)
+        tdt, npdt = torch.float32, np.float32
+    say("plan reuse", case)
+    rng = np.random.default_rng(62)
+    dA = reap.DeviceCSR.from_host(A, dtype=tdt)
+    with reap.Plan(tdt) as plan:
+        rp_d, nnz, _ = plan.symbolic(dA, dA)
+        for it in range(3):
+            vals = A.val if it == 0 else rng.uniform(-1, 1, size=A.nnz).astype(npdt)
+            Ai = synth.CSR(A.rows, A.cols, A.row_ptr, A.col, vals)
+            dAi = reap.DeviceCSR(A.rows, A.cols, dA.row_ptr, dA.col, torch.from_numpy(vals).to("cuda"))
+            col_d, val_d = plan.numeric(dAi, dAi, rp_d)
+            torch.cuda.synchronize()
+            ref = oracle.spgemm(Ai, Ai, threads=_threads())
+            compare_full(ref, rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy(), npdt,
+                         "%s reuse %d" % (case, it))
+
+
 # --- index widths -----------------------------------------------------------------
 
 @pytest.mark.parametrize("in_idx,c_idx", [("i64", "i32"), ("i32", "i64"), ("i64", "i64")])
