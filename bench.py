@@ -34,6 +34,9 @@ WORKLOADS = {
     "stencil": "stencil27 64^3: C = A*A, 262144 rows, FP64, CSR int32",
     "uniform": "uniform 2000x2000, 10 nnz/row: C = A*A, FP64, CSR int32",
     "rmat": "R-MAT scale 18 (a,b,c,d = .57,.19,.19,.05), edge factor 16: C = A*A^T, FP32, CSR int32",
+    "batched": "512 independent C = A*B, A and B m x m uniform-random, m lognormal in [1024, 65536] (median 8192), "
+               "density U[1e-3, 1e-2] per product, FP64, CSR int32 operands, int64 C row pointers; run in waves "
+               "whose C fits the HBM budget, each wave one batched call (graph-captured passes)",
 }
 
 
@@ -118,16 +121,195 @@ def calib_copy(gib: float = 1.0, reps: int = 5):
     print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8, "reps": reps}), flush=True)
 
 
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def plan_waves(nnz, budget_bytes, val_bytes):
+    """Greedy packing of products (in order) into waves whose C (int32
+    columns + values) plus an int64 row pointer fits the budget; a product
+    larger than the budget gets a wave of its own."""
+    waves, cur, used = [], [], 0
+    for q, z in enumerate(nnz):
+        need = z * (4 + val_bytes)
+        if cur and used + need > budget_bytes:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(q)
+        used += need
+    if cur:
+        waves.append(cur)
+    return waves
+
+
+def run_batched(args):
+    """The batched workload: every product's operands resident on the device,
+    one symbolic pass over the whole batch sizes C, products are packed into
+    waves that fit the HBM budget, and each wave is one batched call
+    (graph-captured symbolic and numeric).  A step is all waves.  The same
+    products are then run one at a time through the single-product calls for
+    the batched-vs-plain ratio, and sampled rows are checked against the
+    oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2004_13907_amd as reap
+    import synth
+    from paper_2004_13907_amd import autotune
+    from synth.device import erdos_renyi_device
+
+    specs = synth.batched_set(count=args.batch_count)
+    t0 = time.perf_counter()
+    As, Bs = [], []
+    for sp in specs:
+        rp, c, v = erdos_renyi_device(sp.m, sp.m, sp.density, seed=sp.seed * 2 + 1)
+        As.append(reap.DeviceCSR(sp.m, sp.m, rp, c, v))
+        rp, c, v = erdos_renyi_device(sp.m, sp.m, sp.density, seed=sp.seed * 2 + 2)
+        Bs.append(reap.DeviceCSR(sp.m, sp.m, rp, c, v))
+    torch.cuda.synchronize()
+    nnz_ops = sum(A.nnz + B.nnz for A, B in zip(As, Bs))
+    log("operands generated on the device: %d products, %d nnz, %.1f s" % (len(As), nnz_ops, time.perf_counter() - t0))
+
+    # autotuning on a sample of the batch (every 16th product)
+    sample = list(range(0, len(As), 16))
+    sig = "batched-er:n=%d:m=lognormal(8192;1024..65536):d=U(1e-3,1e-2):f64:sample16" % len(As)
+    tune_path = os.path.join(ROOT, "gpurun_out", "autotune.json") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    tuned = autotune.tune([As[q] for q in sample], [Bs[q] for q in sample], torch.float64, sig,
+                          cache_path=tune_path)
+    opts = dict(tuned["options"])
+    log("autotuned options", opts, "(%.3f s on the sample)" % tuned["seconds"])
+
+    # sizing: one symbolic pass over the whole batch gives every nnz(C_q)
+    with reap.Batch(torch.float64, torch.int64, **opts) as b:
+        nnz = b.symbolic(As, Bs)
+        products = list(b.products)
+    total_products = sum(products)
+    waves = plan_waves(nnz, int(args.hbm_budget_gb * 1e9), 8)
+    log("sizing: %d products, %.4g partial products, nnz(C) %.4g, %d waves" % (len(As), total_products, sum(nnz),
+                                                                           len(waves)))
+    batches = [reap.Batch(torch.float64, torch.int64, graph=True, **opts) for _ in waves]
+    # one C buffer (columns, values) sized for the largest wave, reused by every wave
+    wave_nnz = [sum(nnz[q] for q in w) for w in waves]
+    c_col = torch.empty(max(max(wave_nnz), 1), dtype=torch.int32, device="cuda")
+    c_val = torch.empty(max(max(wave_nnz), 1), dtype=torch.float64, device="cuda")
+    wave_ms = [0.0] * len(waves)
+
+    def step():
+        for wi, (w, b) in enumerate(zip(waves, batches)):
+            t = time.perf_counter()
+            wa, wb = [As[q] for q in w], [Bs[q] for q in w]
+            b.symbolic(wa, wb)
+            b.numeric(wa, wb, out=(c_col, c_val))
+            b.synchronize()
+            wave_ms[wi] = (time.perf_counter() - t) * 1e3
+
+    for _ in range(args.warmup):
+        step()
+        log("warmup step done", ["%.0f" % x for x in wave_ms])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        log("timed step done (ms per wave)", ["%.0f" % x for x in wave_ms])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    gflops = 2.0 * total_products * args.steps / elapsed / 1e9
+
+    plain = None
+    if not args.no_plain:
+        # the same products one at a time through the single-product calls
+        stream = torch.cuda.Stream()
+        rp_buf = torch.empty(max(s.m for s in specs) + 1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            with reap.Plan(torch.float64, torch.int64, stream=stream, **opts) as plan:
+                for A, B in zip(As, Bs):
+                    rp = rp_buf[:A.rows + 1]
+                    _, z, _ = plan.symbolic(A, B, rp)
+                    plan.numeric(A, B, rp, c_col[:z], c_val[:z])
+        stream.synchronize()
+        plain_s = time.perf_counter() - t0
+        plain = {"seconds": round(plain_s, 4), "GFLOP/s": round(2.0 * total_products / plain_s / 1e9, 3),
+                 "batched_over_plain": round(plain_s / (ms_step * 1e-3), 3)}
+        log("plain one-at-a-time: %.3f s" % plain_s)
+
+    # sampled parity: three products (smallest, median, largest work), 64 rows each
+    order = np.argsort(np.asarray(products))
+    chk = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    worst = 0.0
+    with reap.Batch(torch.float64, torch.int64, **opts) as b:
+        b.symbolic([As[q] for q in chk], [Bs[q] for q in chk])
+        res = b.numeric([As[q] for q in chk], [Bs[q] for q in chk])
+        b.synchronize()
+        rng = np.random.default_rng(4)
+        for q, C in zip(chk, res):
+            Ah = synth.CSR(As[q].rows, As[q].cols, As[q].row_ptr.cpu().numpy(), As[q].col.cpu().numpy(),
+                           As[q].val.cpu().numpy())
+            Bh = synth.CSR(Bs[q].rows, Bs[q].cols, Bs[q].row_ptr.cpu().numpy(), Bs[q].col.cpu().numpy(),
+                           Bs[q].val.cpu().numpy())
+            rows = np.sort(rng.choice(Ah.rows, size=min(64, Ah.rows), replace=False))
+            ref = oracle.spgemm(Ah, Bh, rows=rows, threads=min(16, oracle.max_threads()))
+            rp = C.row_ptr.cpu().numpy().astype(np.int64)
+            idx = np.concatenate([np.arange(rp[i], rp[i + 1]) for i in rows])
+            sel = torch.from_numpy(idx).to(C.col.device)
+            gcol = C.col.index_select(0, sel).cpu().numpy()
+            gval = C.val.index_select(0, sel).cpu().numpy()
+            assert np.array_equal(np.diff(ref.row_ptr), rp[rows + 1] - rp[rows]), "batched: row lengths differ"
+            assert np.array_equal(gcol, ref.col), "batched: columns differ"
+            nzs = ref.sabs > 0
+            err = np.abs(gval - ref.val)
+            worst = max(worst, float((err[nzs] / ref.sabs[nzs]).max()) if nzs.any() else 0.0)
+            assert np.all(gval[~nzs] == 0.0)
+    assert worst <= 1e-12, "batched: value error %.3e" % worst
+    log("sampled parity ok (max scaled error %.2e)" % worst)
+
+    out = {
+        "metric": "SpGEMM GFLOP/s (2 x partial products per second)",
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (operands generated on the device, see synth/device.py)",
+        "config": {"workload": WORKLOADS["batched"], "products": len(As), "partial_products": total_products,
+                   "nnz_C": int(sum(nnz)), "waves": len(waves), "hbm_budget_GB": args.hbm_budget_gb,
+                   "wave_products": [len(w) for w in waves], "wave_ms": [round(x, 2) for x in wave_ms],
+                   "autotuned_options": opts},
+        "plain": plain,
+        "parity_sample": {"products": chk, "rows_each": 64, "max_scaled_error": worst},
+    }
+    for b in batches:
+        b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 2 for batched)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 5; 1 for batched)")
     ap.add_argument("--workload", default="stencil", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="only run the counter-calibration copy")
+    ap.add_argument("--batch-count", type=int, default=512, help="products of the batched workload")
+    ap.add_argument("--hbm-budget-gb", type=float, default=120.0,
+                    help="batched: device bytes of C (plus workspace) admitted per wave")
+    ap.add_argument("--no-plain", action="store_true", help="batched: skip the one-product-at-a-time comparison")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 2 if args.workload == "batched" else 20
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "batched" else 5
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -146,6 +328,9 @@ def main():
     torch.cuda.set_device(0)
     if args.calib_copy:
         calib_copy()
+        return
+    if args.workload == "batched":
+        run_batched(args)
         return
 
     A, B, npdt = make_workload(args.workload)

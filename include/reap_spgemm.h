@@ -100,6 +100,8 @@ typedef struct {
  *                        kernel).  Needs a stream other than the legacy
  *                        default stream; ignored with `validate` or with
  *                        REAP_DEBUG_SYNC=1 in the environment.
+ *   long_workgroups_per_cu -- workgroups per compute unit that walk the
+ *                        long-row list (1..8; 0 = default 2).
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -112,7 +114,8 @@ typedef struct {
     int32_t profile;
     int32_t wave_small_values;
     int32_t graph;
-    int32_t reserved[7];
+    int32_t long_workgroups_per_cu;
+    int32_t reserved[6];
 } reap_options_t;
 
 /* Per-class row counts of the last symbolic pass (how rows were binned). */

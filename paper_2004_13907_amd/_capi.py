@@ -60,7 +60,8 @@ class reap_options_t(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("wave_small_values", ctypes.c_int32),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("long_workgroups_per_cu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 

@@ -65,6 +65,7 @@ struct reap_spgemm_s {
     bool profile = false;
     bool use_graph = false;   // capture each pass into a HIP graph, replay while the shape repeats
     bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
+    int long_wg_per_cu = 2;   // workgroups per CU walking the long-row list
 
     Workspace ws;      // counters, per-row arrays, tables
     Workspace gvals;   // long-row FP64 accumulators (FP32 output only)
@@ -372,7 +373,8 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
         // the long-row count is known on the device only: a fixed grid walks the list
-        const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * 2));
+        const int lgrid =
+            (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * p->long_wg_per_cu));
         hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_long_sym");
@@ -565,9 +567,9 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
         max_group_nnz = std::max(max_group_nnz, h.max_group_nnz);
     }
 
-    // long rows: the list is walked by up to two workgroups per CU; FP32 output
+    // long rows: the list is walked by long_wg_per_cu workgroups per CU; FP32 output
     // needs an FP64 accumulator per workgroup (one segment of the widest row)
-    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus * 2));
+    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus * p->long_wg_per_cu));
     p->gvals_stride = 0;
     if (p->dtype == REAP_F32 && nl > 0) {
         const int64_t stride =
@@ -762,6 +764,7 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     p->th.wave_hash_products = clampi(o.wave_hash_products, 0, kWaveHashProducts, kWaveHashProducts);
     p->th.wave_small_nnz = clampi(o.wave_small_values, 0, kWaveSmallNnz, kWaveSmallNnz);
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
+    p->long_wg_per_cu = clampi(o.long_workgroups_per_cu, 1, 8, 2);
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
