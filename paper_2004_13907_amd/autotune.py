@@ -69,15 +69,31 @@ def time_batch(As, Bs, dtype, options, reps=2, stream=None) -> float:
     return times[len(times) // 2]
 
 
+# Results measured on an MI355X, shipped with the package and consulted when
+# the user cache has no entry for a signature.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def lookup(signature: str, cache_path: str | None = None):
+    """Cached entry for `signature` (user cache first, then the shipped one), or None."""
+    for path in (cache_path or default_cache_path(), SHIPPED):
+        entry = _load(path).get(signature)
+        if entry:
+            return entry
+    return None
+
+
 def tune(As, Bs, dtype, signature: str, cache_path: str | None = None, reps: int = 2,
          candidates=CANDIDATES, force: bool = False) -> dict:
-    """Options for this workload: from the cache when `signature` is there
-    (unless `force`), else measured over `candidates` on (As, Bs) and cached.
-    Returns {"options": ..., "seconds": ..., "trials": [...]}."""
+    """Options for this workload: from a cache when `signature` is there
+    (unless `force`), else measured over `candidates` on (As, Bs) and written
+    to the user cache.  Returns {"options": ..., "seconds": ..., "trials": [...]}."""
     path = cache_path or default_cache_path()
+    if not force:
+        entry = lookup(signature, path)
+        if entry:
+            return entry
     cache = _load(path)
-    if not force and signature in cache:
-        return cache[signature]
     trials = []
     for opts in candidates:
         s = time_batch(As, Bs, dtype, opts, reps=reps)
