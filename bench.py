@@ -37,6 +37,10 @@ WORKLOADS = {
     "batched": "512 independent C = A*B, A and B m x m uniform-random, m lognormal in [1024, 65536] (median 8192), "
                "density U[1e-3, 1e-2] per product, FP64, CSR int32 operands, int64 C row pointers; run in waves "
                "whose C fits the HBM budget, each wave one batched call (graph-captured passes)",
+    "served": "open-loop Poisson arrivals of jobs drawn 40/40/20 from stencil27 g in [16, 64] (A*A, FP64), R-MAT "
+              "scale 12-18 (A*A^T, FP32) and uniform-random m lognormal in [1024, 65536], d in [1e-3, 1e-2] (FP64); "
+              "operands resident on the device; continuous batching on 4 streams, admission by the symbolic "
+              "pass's exact footprint",
 }
 
 
@@ -292,6 +296,115 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_served(args):
+    """The served workload: a pool of jobs of the configured mix is built on
+    the device; each job is first timed alone (single-product calls, the
+    plain reference); the closed-loop saturation rate of the serving loop is
+    measured with every request queued at once; then open-loop Poisson
+    traces at 0.5x and 0.8x that rate report p50/p99 latency (arrival to
+    completion on the device) and sustained GFLOP/s."""
+    import numpy as np
+    import torch
+
+    import paper_2004_13907_amd as reap
+    import synth
+    from paper_2004_13907_amd.serve import Request, Server
+    from synth.device import erdos_renyi_device
+
+    specs = synth.served_jobs(args.serve_pool, qps=1.0)
+    pool = []
+    t0 = time.perf_counter()
+    for sp in specs:
+        if sp.kind == "uniform":
+            rp, c, v = erdos_renyi_device(sp.size, sp.size, sp.density, seed=sp.seed * 2 + 1)
+            A = reap.DeviceCSR(sp.size, sp.size, rp, c, v)
+            rp, c, v = erdos_renyi_device(sp.size, sp.size, sp.density, seed=sp.seed * 2 + 2)
+            B = reap.DeviceCSR(sp.size, sp.size, rp, c, v)
+        else:
+            Ah, Bh = sp.materialize()
+            tdt = torch.float32 if sp.kind == "rmat" else torch.float64
+            A = reap.DeviceCSR.from_host(Ah, dtype=tdt)
+            B = A if Bh is Ah else reap.DeviceCSR.from_host(Bh, dtype=tdt)
+        pool.append((sp.kind, sp.size, A, B))
+    torch.cuda.synchronize()
+    log("pool of %d jobs built in %.1f s: %s" % (len(pool), time.perf_counter() - t0,
+                                                 [(k, s) for k, s, _, _ in pool]))
+
+    # each job alone through the single-product calls (warm, median of 3)
+    alone_s, prods = [], []
+    stream = torch.cuda.Stream()
+    for kind, size, A, B in pool:
+        ts = []
+        with torch.cuda.stream(stream):
+            with reap.Plan(A.dtype, torch.int64, stream=stream) as plan:
+                for r in range(4):
+                    stream.synchronize()
+                    t = time.perf_counter()
+                    rp, z, pr = plan.symbolic(A, B)
+                    col, val = plan.numeric(A, B, rp)
+                    stream.synchronize()
+                    if r:
+                        ts.append(time.perf_counter() - t)
+                    del rp, col, val
+        ts.sort()
+        alone_s.append(ts[1])
+        prods.append(pr)
+    plain_gflops = 2.0 * sum(prods) / sum(alone_s) / 1e9
+    log("alone: %.3f s for the pool, %.2f GFLOP/s" % (sum(alone_s), plain_gflops))
+
+    budget = 0.6 * torch.cuda.get_device_properties(0).total_memory
+
+    def trace(n, qps, seed):
+        rng = np.random.default_rng(seed)
+        t = np.cumsum(rng.exponential(1.0 / qps, size=n)) if qps else np.zeros(n)
+        pick = rng.integers(0, len(pool), size=n)
+        return [Request(i, pool[p][2], pool[p][3], float(t[i]), kind=pool[p][0]) for i, p in enumerate(pick)]
+
+    def serve(reqs):
+        srv = Server(slots=args.serve_slots, hbm_budget_bytes=budget, max_batch=16, keep_results=False)
+        try:
+            return srv.run(reqs)
+        finally:
+            srv.close()
+
+    serve(trace(min(len(pool), 16), 0, 1))            # warm-up (plans, graphs of the allocator)
+    sat = serve(trace(args.serve_requests, 0, 2))     # closed loop: everything queued at t = 0
+    sat_qps = sat.requests / sat.seconds
+    log("saturation: %.1f jobs/s, %.2f GFLOP/s" % (sat_qps, sat.gflops))
+    levels = {}
+    for frac in (0.5, 0.8):
+        st = serve(trace(args.serve_requests, frac * sat_qps, 3 + int(frac * 10)))
+        levels["%.1fx" % frac] = {"qps": round(frac * sat_qps, 2), "p50_ms": round(st.p50_ms, 3),
+                                  "p99_ms": round(st.p99_ms, 3), "GFLOP/s": round(st.gflops, 3),
+                                  "mean_batch": round(st.mean_batch, 2), "batches": st.batches,
+                                  "per_kind": st.per_kind, "peak_GB": round(st.peak_bytes / 1e9, 2)}
+        log("load %.1fx: p50 %.2f ms p99 %.2f ms, %.2f GFLOP/s" % (frac, st.p50_ms, st.p99_ms, st.gflops))
+    main_level = levels["0.8x"]
+    out = {
+        "metric": "served SpGEMM GFLOP/s (2 x partial products per second, sustained at 0.8x saturation)",
+        "value": main_level["GFLOP/s"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.serve_requests,
+        "warmup": 1,
+        "ms_per_step": round(1e3 / main_level["qps"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (stencil, uniform) / f32 with f64 accumulate (R-MAT)",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["served"], "pool_jobs": len(pool), "requests_per_level": args.serve_requests,
+                   "slots": args.serve_slots, "hbm_budget_GB": round(budget / 1e9, 1)},
+        "latency_ms": {"p50": main_level["p50_ms"], "p99": main_level["p99_ms"]},
+        "levels": levels,
+        "saturation": {"jobs_per_s": round(sat_qps, 2), "GFLOP/s": round(sat.gflops, 3),
+                       "mean_batch": round(sat.mean_batch, 2)},
+        "plain": {"GFLOP/s": round(plain_gflops, 3), "pool_seconds_alone": round(sum(alone_s), 4),
+                  "served_over_plain_at_saturation": round(sat.gflops / plain_gflops, 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +418,9 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0,
                     help="batched: device bytes of C (plus workspace) admitted per wave")
     ap.add_argument("--no-plain", action="store_true", help="batched: skip the one-product-at-a-time comparison")
+    ap.add_argument("--serve-pool", type=int, default=32, help="served: distinct jobs (operand sets) in the pool")
+    ap.add_argument("--serve-requests", type=int, default=240, help="served: requests per load level")
+    ap.add_argument("--serve-slots", type=int, default=4, help="served: concurrent batches (streams)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 2 if args.workload == "batched" else 20
@@ -331,6 +447,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "served":
+        run_served(args)
         return
 
     A, B, npdt = make_workload(args.workload)

@@ -326,8 +326,10 @@ class Batch:
     def _ctx(self):
         return torch.cuda.stream(self.stream) if self.stream is not None else _NullCtx()
 
-    def symbolic(self, As, Bs):
-        """Per-product nnz(C_q); row pointers are written on the device."""
+    def symbolic(self, As, Bs, fresh: bool = False):
+        """Per-product nnz(C_q); row pointers are written on the device, into
+        a buffer the batch reuses call after call, or (``fresh=True``) into a
+        new one that results of later calls do not overwrite."""
         if len(As) != len(Bs) or not As:
             raise ValueError("need equally many (and at least one) A and B operands")
         for A, B in zip(As, Bs):
@@ -335,7 +337,7 @@ class Batch:
         total = sum(A.rows + 1 for A in As)
         dev = As[0].row_ptr.device
         with self._ctx():
-            if self._rp is None or self._rp.numel() < total or self._rp.dtype != self.c_index_dtype:
+            if fresh or self._rp is None or self._rp.numel() < total or self._rp.dtype != self.c_index_dtype:
                 self._rp = torch.empty(total, dtype=self.c_index_dtype, device=dev)
         views, o = [], 0
         for A in As:
