@@ -28,6 +28,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, published peak
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_2004_13907_amd/csrc/kernels_numeric.h", "paper_2004_13907_amd/csrc/kernels_symbolic.h",
+                  "paper_2004_13907_amd/csrc/kernels_wave.h", "paper_2004_13907_amd/csrc/kernels_long.h",
+                  "paper_2004_13907_amd/csrc/kernels_scan.h", "paper_2004_13907_amd/csrc/reap_spgemm.hip",
                   "paper_2004_13907_amd/csrc/device_utils.h", "paper_2004_13907_amd/csrc/spgemm_common.h"]
 
 WORKLOADS = {

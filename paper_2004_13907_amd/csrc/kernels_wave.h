@@ -303,7 +303,8 @@ __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan&
 // LDS hash set when the row has at most th.wave_hash_products products.  Rows
 // with more than 64 entries or th.wave_max_products products go to the
 // long-row list.
-template <typename IdxT>
+// TAB: arguments from the batch table (else the by-value argument of a single product).
+template <typename IdxT, bool TAB>
 __global__ void __launch_bounds__(kWaveKernelWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
 k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     constexpr int W = kWaveKernelWaves;
@@ -316,9 +317,9 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
-    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
-    const SymArgs<IdxT> p = P ? P[q] : p0;
+    const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const SymArgs<IdxT> p = TAB ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     uint32_t* bits = s_bits[w];
     RowTable<IdxT>& tb = s_tb[w];
@@ -478,7 +479,7 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
 // words, at most NCMAX entries).  The bitmap word and its prefix count share
 // one 64-bit LDS slot, so a column's rank (its position in the sorted row) is
 // one LDS read plus a popcount.
-template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT, int W>
+template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT, int W, bool TAB>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
     __shared__ uint2 s_bp[W][padded_words(WMAX)];  // .x bitmap word, .y set bits before it (padded, + dummy)
@@ -496,9 +497,9 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
     WaveStage<IdxT>& st = s_stage[w];
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
-    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
-    const NumArgs<T, IdxT, IdxC> p = P ? P[q] : p0;
+    const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const NumArgs<T, IdxT, IdxC> p = TAB ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool mine = lane < nrows && p.cls[row0 + lane] == want;
@@ -527,7 +528,7 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
 // (at most kWaveHashProducts products): LDS hash table keyed by column, then
 // the occupied slots are compacted and each entry is placed by counting the
 // smaller columns.
-template <typename T, typename IdxT, typename IdxC, int W>
+template <typename T, typename IdxT, typename IdxC, int W, bool TAB>
 __global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P,
                                                           BatchMap bm, uint8_t want) {
     constexpr int MAXIT = kWaveHashIt;
@@ -549,9 +550,9 @@ __global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC>
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
-    const int q = bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
-    const int blk = gb - (bm.nprod > 1 ? bm.blk_start[q] : 0);
-    const NumArgs<T, IdxT, IdxC> p = P ? P[q] : p0;
+    const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
+    const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
+    const NumArgs<T, IdxT, IdxC> p = TAB ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool mine = lane < nrows && p.cls[row0 + lane] == want;

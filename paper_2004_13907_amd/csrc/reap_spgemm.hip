@@ -368,8 +368,12 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
 
     ev_record(p, kPhSymbolic, false);
     if (p->total_blocks > 0) {
-        hipLaunchKernelGGL(k_sym_wave<IdxT>, dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0, p->stream, a0,
-                           P, bm);
+        if (tab)
+            hipLaunchKernelGGL((k_sym_wave<IdxT, true>), dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0,
+                               p->stream, a0, P, bm);
+        else
+            hipLaunchKernelGGL((k_sym_wave<IdxT, false>), dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0,
+                               p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
         // the long-row count is known on the device only: a fixed grid walks the list
@@ -618,17 +622,26 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     ev_record(p, kPhNumAll, false);
     ev_record(p, kPhNumWave, false);
     if (p->agg.cls[kClsWaveBmpS] > 0) {
-        hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS>),
-                           dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm,
-                           (uint8_t)kClsWaveBmpS);
+        if (tab)
+            hipLaunchKernelGGL(
+                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS, true>),
+                dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
+        else
+            hipLaunchKernelGGL(
+                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS, false>),
+                dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_bmp");
     }
     ev_record(p, kPhNumWave, true);
     ev_record(p, kPhNumHash, false);
     if (p->agg.cls[kClsWaveHash] > 0) {
-        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH>), dim3(p->total_blocks),
-                           dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
+        if (tab)
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true>), dim3(p->total_blocks),
+                               dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
+        else
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false>), dim3(p->total_blocks),
+                               dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_hash");
     }
