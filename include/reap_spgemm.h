@@ -196,6 +196,23 @@ reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t plan, int64_t count, const
                                         const reap_csr_t* B, const void* const* c_row_ptr,
                                         int32_t* const* c_col_idx, void* const* c_values);
 
+/*
+ * Device transpose: T = A^T in CSR (A's compressed-column form), so that a
+ * product A * A^T needs only A on the device.  T has A.cols rows and A.cols
+ * + 1 row pointers of A's row-pointer type (t_row_ptr, device); t_col_idx
+ * (int32) and t_values (the plan's dtype) are device arrays of A.nnz
+ * elements.  Inside a row of T the entries keep A's row order, so T's
+ * columns are ascending whenever A's rows are stored in order (every
+ * canonical CSR input); entries of A that repeat a position stay separate
+ * and keep their order.  The paper's row-reorganised input format reads the
+ * second operand by columns (Section III-A); this is that change of
+ * direction done on the device.  Asynchronous on the plan's stream; the plan
+ * keeps scratch of about 20 bytes per entry of A.
+ * Errors: INVALID_ARG (nulls, A.nnz or A.rows above INT32_MAX), OUT_OF_MEMORY, HIP.
+ */
+reap_status_t reap_csr_transpose(reap_spgemm_t plan, const reap_csr_t* A, void* t_row_ptr,
+                                 int32_t* t_col_idx, void* t_values);
+
 /* Release the plan's workspace and the plan (NULL is accepted). */
 reap_status_t reap_spgemm_destroy(reap_spgemm_t plan);
 

@@ -32,6 +32,8 @@ __all__ = [
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
+    "reap_csr_transpose",
+    "transpose",
     "reap_spgemm_destroy",
     "reap_spgemm_bin_stats",
     "reap_spgemm_phase_times",
@@ -200,6 +202,14 @@ def reap_spgemm_batch_numeric(plan, As, Bs, c_row_ptrs, c_cols, c_vals) -> int:
     cc = (ctypes.c_void_p * n)(*[(t.data_ptr() if t.numel() else None) for t in c_cols])
     cv = (ctypes.c_void_p * n)(*[(t.data_ptr() if t.numel() else None) for t in c_vals])
     return lib.reap_spgemm_batch_numeric(plan, n, a, b, rp, cc, cv)
+
+
+def reap_csr_transpose(plan, A: DeviceCSR, t_row_ptr: torch.Tensor, t_col: torch.Tensor, t_val: torch.Tensor) -> int:
+    lib = _capi.load()
+    a = A.c_struct()
+    return lib.reap_csr_transpose(plan, ctypes.byref(a), ctypes.c_void_p(t_row_ptr.data_ptr()),
+                                  ctypes.c_void_p(t_col.data_ptr() if t_col.numel() else None),
+                                  ctypes.c_void_p(t_val.data_ptr() if t_val.numel() else None))
 
 
 def reap_spgemm_destroy(plan) -> int:
@@ -404,6 +414,27 @@ def spgemm_batch(As, Bs, dtype=None, c_index_dtype=torch.int32, graph: bool = Fa
         out = b.numeric(As, Bs)
         b.synchronize()
     return out
+
+
+def transpose(A: DeviceCSR, plan: Plan | None = None) -> DeviceCSR:
+    """A^T on the device (row pointers of A's index type).  Asynchronous on the
+    plan's stream (torch's current stream for a temporary plan, which is
+    synchronised before it is released)."""
+    own = plan is None
+    if own:
+        plan = Plan(A.dtype, torch.int32)
+    try:
+        dev = A.row_ptr.device
+        rp = torch.empty(A.cols + 1, dtype=A.row_ptr.dtype, device=dev)
+        col = torch.empty(A.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(A.nnz, dtype=A.dtype, device=dev)
+        st = reap_csr_transpose(plan.handle, A, rp, col, val)
+        if st != REAP_OK:
+            raise SpGEMMError(st, "reap_csr_transpose")
+        return DeviceCSR(A.cols, A.rows, rp, col, val)
+    finally:
+        if own:
+            plan.close()
 
 
 def spgemm(A: DeviceCSR, B: DeviceCSR, c_index_dtype=None, plan: Plan | None = None, **options) -> DeviceCSR:

@@ -28,6 +28,7 @@ EXPORTED = (
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
+    "reap_csr_transpose",
     "reap_spgemm_destroy",
     "reap_spgemm_bin_stats",
     "reap_spgemm_phase_times",
@@ -108,6 +109,8 @@ def load():
     lib.reap_spgemm_batch_numeric.argtypes = [P, ctypes.c_int64, ctypes.POINTER(reap_csr_t),
                                               ctypes.POINTER(reap_csr_t), PP, PP, PP]
     lib.reap_spgemm_batch_numeric.restype = st
+    lib.reap_csr_transpose.argtypes = [P, ctypes.POINTER(reap_csr_t), P, P, P]
+    lib.reap_csr_transpose.restype = st
     lib.reap_spgemm_destroy.argtypes = [P]
     lib.reap_spgemm_destroy.restype = st
     lib.reap_spgemm_bin_stats.argtypes = [P, ctypes.POINTER(reap_bin_stats_t)]

@@ -19,6 +19,7 @@
 #include "kernels_numeric.h"
 #include "kernels_scan.h"
 #include "kernels_symbolic.h"
+#include "kernels_transpose.h"
 #include "kernels_wave.h"
 #include "spgemm_common.h"
 
@@ -69,6 +70,7 @@ struct reap_spgemm_s {
 
     Workspace ws;      // counters, per-row arrays, tables
     Workspace gvals;   // long-row FP64 accumulators (FP32 output only)
+    Workspace tws;     // scratch of the device transpose
     int64_t cap_rows = -1, cap_prods = 0;
     int32_t cap_blocks = 0, cap_tiles = 0;
     uint64_t ws_generation = 0;
@@ -732,6 +734,124 @@ reap_status_t numeric_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A
     return numeric_typed<float, int64_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
 }
 
+// ---------------------------------------------------------------------------
+// Device transpose.
+
+template <typename IdxC>
+reap_status_t launch_scan(reap_spgemm_s* p, const int32_t* counts, int64_t m, long long* tiles, Counters* dummy,
+                          void* out) {
+    ScanArgs s{};
+    s.rnnz = counts;
+    s.m = m;
+    s.tiles = tiles;
+    s.ntiles = (int32_t)((m + kScanTile - 1) / kScanTile);
+    s.nparts = 0;
+    s.parts = nullptr;
+    s.ctr = dummy;
+    s.c_rp = out;
+    ScanMap sm;
+    sm.tile_start = nullptr;
+    sm.nprod = 1;
+    if (s.ntiles > 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(s.ntiles), dim3(kScanThreads), 0, p->stream, s, nullptr, sm);
+        REAP_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_scan_spine<IdxC>, dim3(1), dim3(1024), 0, p->stream, s, nullptr);
+    REAP_LAUNCH_CHECK();
+    if (s.ntiles > 0) {
+        hipLaunchKernelGGL(k_scan_apply<IdxC>, dim3(s.ntiles), dim3(kScanThreads), 0, p->stream, s, nullptr, sm);
+        REAP_LAUNCH_CHECK();
+    }
+    return REAP_OK;
+}
+
+template <typename T, typename IdxT>
+reap_status_t transpose_typed(reap_spgemm_s* p, const reap_csr_t* A, void* t_row_ptr, int32_t* t_col, void* t_val) {
+    const int64_t m = A->rows, n = A->cols, nnz = A->nnz;
+    const int64_t ntiles = (nnz + kRsTile - 1) / kRsTile;
+    const int64_t nh = (int64_t)kRsBins * ntiles;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_row = carve((size_t)nnz * 4);
+    const size_t o_k0 = carve((size_t)nnz * 4), o_v0 = carve((size_t)nnz * 4);
+    const size_t o_k1 = carve((size_t)nnz * 4), o_v1 = carve((size_t)nnz * 4);
+    const size_t o_cnt = carve((size_t)(n + 1) * 4);
+    const size_t o_h = carve((size_t)(nh + 1) * 4), o_off = carve((size_t)(nh + 1) * 4);
+    const size_t o_t1 = carve((size_t)((n + kScanTile) / kScanTile + 1) * 8);
+    const size_t o_t2 = carve((size_t)((nh + kScanTile) / kScanTile + 1) * 8);
+    const size_t o_c = carve(sizeof(Counters));
+    if (off > p->tws.bytes) {
+        (void)hipStreamSynchronize(p->stream);
+        if (p->tws.base) (void)hipFree(p->tws.base);
+        p->tws.base = nullptr;
+        p->tws.bytes = 0;
+        if (hipMalloc(&p->tws.base, off) != hipSuccess) {
+            (void)hipGetLastError();
+            return REAP_ERR_OUT_OF_MEMORY;
+        }
+        p->tws.bytes = off;
+    }
+    char* b = static_cast<char*>(p->tws.base);
+    int32_t* rowid = reinterpret_cast<int32_t*>(b + o_row);
+    int32_t* keys[2] = {reinterpret_cast<int32_t*>(b + o_k0), reinterpret_cast<int32_t*>(b + o_k1)};
+    int32_t* vals[2] = {reinterpret_cast<int32_t*>(b + o_v0), reinterpret_cast<int32_t*>(b + o_v1)};
+    int32_t* cnt = reinterpret_cast<int32_t*>(b + o_cnt);
+    int32_t* hist = reinterpret_cast<int32_t*>(b + o_h);
+    int32_t* offs = reinterpret_cast<int32_t*>(b + o_off);
+    long long* t1 = reinterpret_cast<long long*>(b + o_t1);
+    long long* t2 = reinterpret_cast<long long*>(b + o_t2);
+    Counters* dummy = reinterpret_cast<Counters*>(b + o_c);
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((nnz + 255) / 256, (int64_t)p->num_cus * 16));
+
+    // row pointer of the transpose: column counts, exclusive scan
+    const int gz = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, (int64_t)p->num_cus * 16));
+    hipLaunchKernelGGL(k_tr_zero, dim3(gz), dim3(256), 0, p->stream, cnt, n);
+    REAP_LAUNCH_CHECK();
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_tr_colcount, dim3(g), dim3(256), 0, p->stream, A->col_idx, nnz, cnt);
+        REAP_LAUNCH_CHECK();
+    }
+    reap_status_t st = launch_scan<IdxT>(p, cnt, n, t1, dummy, t_row_ptr);
+    if (st != REAP_OK) return st;
+    debug_step(p, "transpose row pointer");
+    if (nnz == 0) return REAP_OK;
+
+    // entries ordered by column (stable: A's row order is kept inside a column)
+    if (m > 0) {
+        hipLaunchKernelGGL(k_tr_rowid<IdxT>, dim3((unsigned)((m * kWave + 255) / 256)), dim3(256), 0, p->stream,
+                           static_cast<const IdxT*>(A->row_ptr), m, rowid);
+        REAP_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_tr_iota, dim3(g), dim3(256), 0, p->stream, vals[0], nnz);
+    REAP_LAUNCH_CHECK();
+    const int bits = n <= 1 ? 0 : 32 - __builtin_clz((unsigned)(n - 1));
+    const int passes = (bits + 7) / 8;
+    const int32_t* kin = A->col_idx;
+    const int32_t* vin = vals[0];
+    int cur = 1;
+    for (int ps = 0; ps < passes; ++ps) {
+        hipLaunchKernelGGL(k_rs_count, dim3((unsigned)ntiles), dim3(kRsThreads), 0, p->stream, kin, nnz, 8 * ps, hist);
+        REAP_LAUNCH_CHECK();
+        if ((st = launch_scan<int32_t>(p, hist, nh, t2, dummy, offs)) != REAP_OK) return st;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, p->stream, kin, vin, nnz,
+                           8 * ps, offs, keys[cur], vals[cur]);
+        REAP_LAUNCH_CHECK();
+        kin = keys[cur];
+        vin = vals[cur];
+        cur ^= 1;
+    }
+    debug_step(p, "transpose sort");
+    hipLaunchKernelGGL((k_tr_gather<T>), dim3(g), dim3(256), 0, p->stream, vin, nnz, rowid,
+                       static_cast<const T*>(A->values), t_col, static_cast<T*>(t_val));
+    REAP_LAUNCH_CHECK();
+    debug_step(p, "transpose gather");
+    return REAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -807,6 +927,7 @@ reap_status_t reap_spgemm_destroy(reap_spgemm_t p) {
     release_graphs(p);
     if (p->ws.base) (void)hipFree(p->ws.base);
     if (p->gvals.base) (void)hipFree(p->gvals.base);
+    if (p->tws.base) (void)hipFree(p->tws.base);
     if (p->h_ctr) (void)hipHostFree(p->h_ctr);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
@@ -844,6 +965,21 @@ reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t p, int64_t count, const re
                                         const void* const* c_row_ptr, int32_t* const* c_col_idx,
                                         void* const* c_values) {
     return numeric_batch(p, count, A, B, c_row_ptr, c_col_idx, c_values);
+}
+
+reap_status_t reap_csr_transpose(reap_spgemm_t p, const reap_csr_t* A, void* t_row_ptr, int32_t* t_col_idx,
+                                 void* t_values) {
+    if (!p || !A || !t_row_ptr) return REAP_ERR_INVALID_ARG;
+    reap_status_t st;
+    if ((st = check_csr(A)) != REAP_OK) return st;
+    if (A->nnz > INT32_MAX || A->rows > INT32_MAX) return REAP_ERR_INVALID_ARG;  // int32 entry and row ids
+    if (A->nnz > 0 && (!t_col_idx || !t_values)) return REAP_ERR_INVALID_ARG;
+    const bool i32 = A->row_ptr_type == REAP_I32;
+    if (p->dtype == REAP_F64)
+        return i32 ? transpose_typed<double, int32_t>(p, A, t_row_ptr, t_col_idx, t_values)
+                   : transpose_typed<double, int64_t>(p, A, t_row_ptr, t_col_idx, t_values);
+    return i32 ? transpose_typed<float, int32_t>(p, A, t_row_ptr, t_col_idx, t_values)
+               : transpose_typed<float, int64_t>(p, A, t_row_ptr, t_col_idx, t_values);
 }
 
 reap_status_t reap_spgemm_bin_stats(reap_spgemm_t p, reap_bin_stats_t* out) {
