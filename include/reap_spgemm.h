@@ -86,8 +86,12 @@ typedef struct {
  *                        and wider windows are processed segment by segment
  *                        (<= 262144, rounded down to a multiple of 32, at
  *                        least 32; 0 = default 262144).
- *   group_lds_values  -- accepted for compatibility and ignored: long rows
- *                        accumulate their values in device memory.
+ *   group_lds_values  -- FP64 accumulator slots in LDS for a long row (256 ..
+ *                        8192; 0 = default 8192).  A long row's window
+ *                        segment whose entries fit is summed in LDS in one
+ *                        walk; a larger one in chunks of this many
+ *                        consecutive entries, when the long B rows it reads
+ *                        are in column order, else in device memory.
  *   profile           -- non-zero: record per-phase device times (see
  *                        reap_spgemm_phase_times).
  *   wave_small_values -- rows of C with at most this many entries (and a
@@ -100,8 +104,9 @@ typedef struct {
  *                        kernel).  Needs a stream other than the legacy
  *                        default stream; ignored with `validate` or with
  *                        REAP_DEBUG_SYNC=1 in the environment.
- *   long_workgroups_per_cu -- workgroups per compute unit that walk the
- *                        long-row list (1..8; 0 = default 2).
+ *   long_workgroups_per_cu -- workgroups per compute unit that take rows
+ *                        from the long-row list in the symbolic pass (1..8;
+ *                        0 = default 2; the numeric pass runs one per CU).
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {

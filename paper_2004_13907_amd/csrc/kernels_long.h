@@ -7,9 +7,10 @@
 // the bitmap words, so that the rank of a column (its position in the sorted
 // row) is one LDS read and a popcount, and adds each product into that slot.
 //
-// Rows are taken from the batch's long-row list of (product, row) pairs with a
-// grid-stride loop (entry j goes to workgroup j mod gridDim.x), so every loop
-// bound is known when the row starts.
+// Rows are taken from the batch's long-row list of (product, row) pairs
+// through a device counter (each workgroup takes the next unprocessed entry
+// when it finishes one), so a few heavy rows do not hold back the workgroups
+// that were handed them together with many others.
 #pragma once
 #include "device_utils.h"
 #include "kernels_symbolic.h"
@@ -18,9 +19,15 @@
 
 namespace reap {
 
-constexpr int kLongThreads = 512;
+constexpr int kLongThreads = 512;       // symbolic pass
 constexpr int kLongWaves = kLongThreads / kWave;
-constexpr int kLongSegWords = 8192;  // 262144 columns per segment
+constexpr int kLongNumThreads = 1024;   // numeric pass (one workgroup per CU: its LDS is ~150 KB)
+constexpr int kLongNumWaves = kLongNumThreads / kWave;
+constexpr int kLongSegWords = 8192;     // 262144 columns per window segment
+constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS
+constexpr int kLongMinVals = 256;       // smallest rank chunk accepted
+constexpr int kLongMaxChunks = kLongSegWords * 32 / kLongMinVals;
+constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a long row's B row is not in column order
 
 // Per-wavefront table of one chunk of (at most 64) A entries.
 template <typename IdxT>
@@ -37,11 +44,15 @@ struct LongChunk {
 // per step.  The other entries of the chunk are taken in groups of G lanes
 // (G the smallest power of two not below the chunk's longest such B row):
 // 64/G entries per step, lane `off` of a group reads B entry b0 + off.
-template <typename IdxT, typename T, bool VALS, typename Fn>
+// Entries whose B row has skip_from or more entries (skip_from >= 64) are
+// not visited.  CHECK sets *unsorted when a B row of 64 or more entries is not
+// in ascending column order.
+template <typename IdxT, typename T, bool VALS, bool CHECK = false, typename Fn>
 __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int32_t* __restrict__ a_col,
                                                   const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
                                                   const int32_t* __restrict__ b_col, int wave, int nwaves,
-                                                  LongChunk<IdxT>& tb, Fn&& fn) {
+                                                  LongChunk<IdxT>& tb, Fn&& fn, bool* unsorted = nullptr,
+                                                  int64_t skip_from = INT64_MAX) {
     const int lane = lane_id();
     for (int64_t ch = (int64_t)wave * kWave; ch < nA; ch += (int64_t)nwaves * kWave) {
         const int cnt = (int)min((int64_t)kWave, nA - ch);
@@ -77,14 +88,18 @@ __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int
             }
             wave_sync();
         }
-        uint64_t lm = ballot(lng);
+        uint64_t lm = ballot(lng && len < skip_from);
         while (lm) {
             const int e = __ffsll((unsigned long long)lm) - 1;
             lm &= lm - 1;
             const int64_t eb0 = (int64_t)shfl(b0, e);
             const int64_t elen = shfl(len, e);
             const double ea = VALS ? shfl(a, e) : 0.0;
-            for (int64_t q = lane; q < elen; q += kWave) fn(b_col[eb0 + q], eb0 + q, ea);
+            for (int64_t q = lane; q < elen; q += kWave) {
+                const int c = b_col[eb0 + q];
+                if (CHECK && q > 0 && b_col[eb0 + q - 1] > c) *unsorted = true;
+                fn(c, eb0 + q, ea);
+            }
         }
     }
 }
@@ -112,10 +127,15 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
     __shared__ LongChunk<IdxT> s_tb[kLongWaves];
     __shared__ long long s_red[kLongWaves];
     __shared__ int s_redi[kLongWaves];
+    __shared__ int s_next;
 
     const int w = threadIdx.x / kWave;
     const int nL = (int)*bm.n_long;
-    for (int j = blockIdx.x; j < nL; j += gridDim.x) {
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[0], 1u);
+        __syncthreads();
+        const int j = s_next;
+        if (j >= nL) break;
         const int2 ent = bm.long_list[j];
         const SymArgs<IdxT> p = P ? P[ent.x] : p0;
         const int seg_cols = p.th.group_lds_span;
@@ -139,24 +159,47 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             span = (cmax >= cmin) ? (int64_t)cmax - cmin + 1 : 0;
         }
         long long nnz = 0;
+        bool unsorted = false;
         for (int64_t s0 = 0; s0 < span; s0 += seg_cols) {
             const int seg_lo = lo + (int)s0;
             const int seg_w = (int)((min((int64_t)seg_cols, span - s0) + 31) >> 5);
             const int seg_hi = seg_lo + seg_w * 32;
             for (int x = threadIdx.x; x < seg_w; x += kLongThreads) s_bits[x] = 0u;
             __syncthreads();
-            long_row_products<IdxT, float, false>(rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
-                                                  [&](int col, int64_t, double) {
-                                                      if (col >= seg_lo && col < seg_hi) {
-                                                          const int d = col - seg_lo;
-                                                          atomicOr(&s_bits[d >> 5], 1u << (d & 31));
-                                                      }
-                                                  });
+            long_row_products<IdxT, float, false, true>(
+                rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
+                [&](int col, int64_t, double) {
+                    if (col >= seg_lo && col < seg_hi) {
+                        const int d = col - seg_lo;
+                        atomicOr(&s_bits[d >> 5], 1u << (d & 31));
+                    }
+                },
+                &unsorted);
             __syncthreads();
             long long pc = 0;
             for (int x = threadIdx.x; x < seg_w; x += kLongThreads) pc += __popc(s_bits[x]);
             nnz += block_sum_i64<kLongThreads>(pc, s_red);
         }
+        if (p.n <= seg_cols && span > 0) {
+            // one segment from column 0: narrow the window to the set bits
+            // (the numeric pass then zeroes, scans and emits fewer words)
+            const int seg_w = (int)((span + 31) >> 5);
+            int cmin = INT32_MAX, cmax = -1;
+            for (int x = threadIdx.x; x < seg_w; x += kLongThreads) {
+                const uint32_t bw = s_bits[x];
+                if (bw) {
+                    cmin = min(cmin, x * 32 + __ffs(bw) - 1);
+                    cmax = max(cmax, x * 32 + 31 - __clz(bw));
+                }
+            }
+            cmin = block_min_i32<kLongThreads>(cmin, s_redi);
+            cmax = block_max_i32<kLongThreads>(cmax, s_redi);
+            lo = cmax >= 0 ? cmin : 0;
+            span = cmax >= 0 ? (int64_t)cmax - cmin + 1 : 0;
+        }
+        // the numeric pass walks long B rows of long rows in column order only
+        // when they are stored that way
+        if (ballot(unsorted) && lane_id() == 0) atomicOr(&p.ctr->bad_csr, kUnsortedB);
         if (threadIdx.x == 0) {
             p.rnnz[i] = (int32_t)nnz;
             p.win[i] = make_int2(lo, (int)span);
@@ -170,28 +213,54 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 }
 
 // ---------------------------------------------------------------------------
-// Numeric pass for the long-row list.  Per segment of the row's window:
-// (1) bitmap of the segment's columns, (2) prefix count of set bits per word
-// (block scan), (3) the segment's slots are cleared and every product is added
-// into the slot of its column's rank with a device-memory FP64 atomic (the
-// row's own output for FP64; a per-workgroup FP64 buffer for FP32, rounded
-// once on the copy out), (4) columns are written from the bitmap in ascending
-// order.  Only this workgroup touches the row's slots during the kernel, so
-// the atomics are workgroup-scoped.
+// Numeric pass for the long-row list, one workgroup of 1024 threads per row.
+// Per segment of the row's window (up to 262144 columns): (1) bitmap of the
+// segment's columns, (2) prefix count of set bits per word (block scan), so
+// the rank of a column -- its position in the sorted row -- is one LDS read
+// and a popcount, (3) accumulation by rank, (4) columns written from the
+// bitmap in ascending order.  Accumulation:
+//  - a segment with at most V = group_lds_values (<= 8192) entries is summed
+//    in LDS in one walk of the products;
+//  - a larger segment is cut into nch chunks of V consecutive ranks (a column
+//    range each).  If the long B rows are in column order (checked by the
+//    symbolic pass), the A entries whose B row has at least max(64, 16 nch)
+//    entries are walked chunk by chunk: a 64-way search finds where the
+//    chunk's column range starts in the B row, the wavefront walks it until
+//    the range ends, and the chunk's LDS sums are added to the segment's
+//    slots in device memory.  The products of the other A entries (short B
+//    rows, which a per-chunk walk would revisit too often) are added into
+//    those slots with FP64 atomics;
+//  - if a long B row is not in column order, every product of the segment is
+//    added into device memory with FP64 atomics.
+// The device slots are C's own values for FP64 and a per-workgroup FP64
+// buffer for FP32 (rounded once on the copy out).  Only this workgroup
+// touches the row's slots, so those atomics are workgroup-scoped.
 template <typename T, typename IdxT, typename IdxC>
-__global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
-                                                          const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm) {
+__global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
+                                                             const NumArgs<T, IdxT, IdxC>* __restrict__ P,
+                                                             BatchMap bm) {
+    constexpr int NT = kLongNumThreads, NW = kLongNumWaves;
     __shared__ uint32_t s_bits[kLongSegWords];
     __shared__ uint32_t s_pfx[kLongSegWords];
-    __shared__ LongChunk<IdxT> s_tb[kLongWaves];
-    __shared__ long long s_red[kLongWaves];
+    __shared__ double s_vals[kLongVals];
+    __shared__ LongChunk<IdxT> s_tb[NW];
+    __shared__ long long s_red[NW];
+    __shared__ int s_bound[kLongMaxChunks + 1];
+    __shared__ int s_next;
 
     const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
     const int nL = (int)*bm.n_long;
-    for (int j = blockIdx.x; j < nL; j += gridDim.x) {
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[1], 1u);
+        __syncthreads();
+        const int j = s_next;
+        if (j >= nL) break;
         const int2 ent = bm.long_list[j];
         const NumArgs<T, IdxT, IdxC> p = P ? P[ent.x] : p0;
         const int seg_cols = p.th.group_lds_span;
+        const int V = min(max(p.th.group_lds_values, kLongMinVals), kLongVals);
+        const bool sorted_b = (p.ctr->bad_csr & kUnsortedB) == 0u;
         const int64_t i = ent.y;
         const IdxT rs = p.a_rp[i];
         const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
@@ -205,9 +274,9 @@ __global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC
             const int seg_lo = lo + (int)s0;
             const int seg_w = (int)((min((int64_t)seg_cols, span - s0) + 31) >> 5);
             const int seg_hi = seg_lo + seg_w * 32;
-            for (int x = threadIdx.x; x < seg_w; x += kLongThreads) s_bits[x] = 0u;
+            for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
             __syncthreads();
-            long_row_products<IdxT, T, false>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
+            long_row_products<IdxT, T, false>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
                                               [&](int col, int64_t, double) {
                                                   if (col >= seg_lo && col < seg_hi) {
                                                       const int d = col - seg_lo;
@@ -216,41 +285,142 @@ __global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC
                                               });
             __syncthreads();
             // thread t owns words [t*per, t*per + per)
-            const int per = (seg_w + kLongThreads - 1) / kLongThreads;
+            const int per = (seg_w + NT - 1) / NT;
             const int w0 = min((int)threadIdx.x * per, seg_w), w1 = min(w0 + per, seg_w);
             long long local = 0;
             for (int x = w0; x < w1; ++x) local += __popc(s_bits[x]);
-            long long seg_nnz;
-            long long run = block_excl_scan_i64<kLongThreads>(local, s_red, &seg_nnz);
+            long long seg_nnz_ll;
+            long long run = block_excl_scan_i64<NT>(local, s_red, &seg_nnz_ll);
             for (int x = w0; x < w1; ++x) {
                 s_pfx[x] = (uint32_t)run;
                 run += __popc(s_bits[x]);
             }
-            if (off + seg_nnz > nc_row) {  // pattern differs from the symbolic pass
+            if (off + seg_nnz_ll > nc_row) {  // pattern differs from the symbolic pass
                 if (threadIdx.x == 0) atomicOr(&p.ctr->bad_csr, 4u);
                 break;
             }
-            double* acc;
-            if constexpr (sizeof(T) == sizeof(double)) {
-                acc = reinterpret_cast<double*>(p.c_val) + cb + off;
+            const int seg_nnz = (int)seg_nnz_ll;
+            auto rank_of = [&](int col) {
+                const int d = col - seg_lo;
+                const int x = d >> 5;
+                return (int)s_pfx[x] + __popc(s_bits[x] & ((1u << (d & 31)) - 1u));
+            };
+            if (seg_nnz <= V) {
+                // the whole segment in LDS
+                for (int x = threadIdx.x; x < seg_nnz; x += NT) s_vals[x] = 0.0;
+                __syncthreads();
+                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
+                                                 [&](int col, int64_t bidx, double a) {
+                                                     if (col >= seg_lo && col < seg_hi)
+                                                         atomicAdd(&s_vals[rank_of(col)], a * (double)p.b_val[bidx]);
+                                                 });
+                __syncthreads();
+                for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)s_vals[x];
             } else {
-                acc = p.gvals + (int64_t)blockIdx.x * p.gvals_stride;
+                double* acc;
+                if constexpr (sizeof(T) == sizeof(double)) {
+                    acc = reinterpret_cast<double*>(p.c_val) + cb + off;
+                } else {
+                    acc = p.gvals + (int64_t)blockIdx.x * p.gvals_stride;
+                }
+                for (int x = threadIdx.x; x < seg_nnz; x += NT) acc[x] = 0.0;
+                __threadfence_block();
+                __syncthreads();
+                const int nch = (seg_nnz + V - 1) / V;
+                // A entries whose B row is at least this long are walked chunk by chunk
+                const int64_t walk_from = sorted_b ? (int64_t)max(kWave, 16 * nch) : INT64_MAX;
+                long_row_products<IdxT, T, true>(
+                    rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
+                    [&](int col, int64_t bidx, double a) {
+                        if (col >= seg_lo && col < seg_hi)
+                            __hip_atomic_fetch_add(&acc[rank_of(col)], a * (double)p.b_val[bidx], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    },
+                    nullptr, walk_from);
+                if (sorted_b) {
+                    // column boundaries of the rank chunks: chunk c holds ranks
+                    // [cV, cV + V), columns [s_bound[c], s_bound[c + 1])
+                    if (threadIdx.x == 0) {
+                        s_bound[0] = seg_lo;
+                        s_bound[nch] = seg_hi;
+                    }
+                    for (int x = w0; x < w1; ++x) {
+                        const int r0 = (int)s_pfx[x];
+                        const uint32_t bw = s_bits[x];
+                        const int c = __popc(bw);
+                        // every multiple of V in [r0, r0 + c) but 0
+                        for (int k = max(1, (r0 + V - 1) / V); k * V < r0 + c; ++k) {
+                            uint32_t m = bw;
+                            for (int t = k * V - r0; t > 0; --t) m &= m - 1;  // drop the lower set bits
+                            s_bound[k] = seg_lo + x * 32 + (__ffs(m) - 1);
+                        }
+                    }
+                    // the atomics of every thread are done before the merges read the
+                    // slots (all of the workgroup's accesses go through one CU, so a
+                    // workgroup-scope fence is enough: an agent-scope one would write
+                    // back and invalidate the whole L2 of the XCD, per row)
+                    __threadfence_block();
+                    __syncthreads();
+                    for (int c = 0; c < nch; ++c) {
+                        const int clo = s_bound[c], chi = s_bound[c + 1];
+                        const int r0 = c * V, rn = min(V, seg_nnz - r0);
+                        for (int x = threadIdx.x; x < rn; x += NT) s_vals[x] = 0.0;
+                        __syncthreads();
+                        for (int64_t ch = (int64_t)w * kWave; ch < nA; ch += (int64_t)NW * kWave) {
+                            const int cnt = (int)min((int64_t)kWave, nA - ch);
+                            int64_t b0 = 0, len = 0;
+                            double a = 0.0;
+                            if (lane < cnt) {
+                                const int k = p.a_col[rs + ch + lane];
+                                const IdxT x0 = p.b_rp[k];
+                                b0 = (int64_t)x0;
+                                len = (int64_t)p.b_rp[k + 1] - (int64_t)x0;
+                                a = (double)p.a_val[rs + ch + lane];
+                            }
+                            uint64_t lm = ballot(len >= walk_from);
+                            while (lm) {
+                                const int e = __ffsll((unsigned long long)lm) - 1;
+                                lm &= lm - 1;
+                                const int64_t eb0 = shfl(b0, e);
+                                const int64_t elen = shfl(len, e);
+                                const double ea = shfl(a, e);
+                                // narrow [qlo, qhi] to at most 64 entries around the first column >= clo
+                                int64_t qlo = 0, qhi = elen;
+                                while (qhi - qlo > kWave) {
+                                    const int64_t step = (qhi - qlo + kWave - 1) / kWave;
+                                    const int64_t probe = qlo + (int64_t)lane * step;
+                                    const bool below = probe < qhi && p.b_col[eb0 + probe] < clo;
+                                    const int nb = __popcll(ballot(below));  // a prefix of the probes (sorted row)
+                                    if (nb == 0) {
+                                        qhi = qlo;
+                                    } else {
+                                        const int64_t nlo = qlo + (int64_t)(nb - 1) * step;
+                                        qhi = min(qhi, qlo + (int64_t)nb * step);
+                                        qlo = nlo;
+                                    }
+                                }
+                                // walk from qlo until the chunk's column range ends
+                                for (int64_t base = qlo; base < elen; base += kWave) {
+                                    const int64_t q = base + lane;
+                                    const int col = q < elen ? p.b_col[eb0 + q] : INT32_MAX;
+                                    if (col >= clo && col < chi)
+                                        atomicAdd(&s_vals[rank_of(col) - r0], ea * (double)p.b_val[eb0 + q]);
+                                    if (ballot(col < chi) != ~0ull) break;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        for (int x = threadIdx.x; x < rn; x += NT) acc[r0 + x] += s_vals[x];
+                        __syncthreads();
+                    }
+                }
+                if constexpr (sizeof(T) != sizeof(double)) {
+                    // the adds of every wavefront are complete before the buffer is read back
+                    __threadfence_block();
+                    __syncthreads();
+                    for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)acc[x];
+                }
             }
-            for (long long x = threadIdx.x; x < seg_nnz; x += kLongThreads) acc[x] = 0.0;
-            __threadfence_block();
-            __syncthreads();
-            long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
-                                             [&](int col, int64_t bidx, double a) {
-                                                 if (col >= seg_lo && col < seg_hi) {
-                                                     const int d = col - seg_lo;
-                                                     const int x = d >> 5;
-                                                     const int rk = (int)s_pfx[x] +
-                                                                    __popc(s_bits[x] & ((1u << (d & 31)) - 1u));
-                                                     __hip_atomic_fetch_add(&acc[rk], a * (double)p.b_val[bidx],
-                                                                            __ATOMIC_RELAXED,
-                                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                                                 }
-                                             });
             for (int x = w0; x < w1; ++x) {
                 uint32_t bw = s_bits[x];
                 int64_t o = cb + off + s_pfx[x];
@@ -260,18 +430,16 @@ __global__ void __launch_bounds__(kLongThreads) k_long_num(NumArgs<T, IdxT, IdxC
                     p.c_col[o++] = seg_lo + x * 32 + b;
                 }
             }
-            if constexpr (sizeof(T) != sizeof(double)) {
-                // the adds of every wavefront must be complete and visible
-                // before the buffer is read back (and L1 holds no stale copy)
-                __threadfence();
-                __syncthreads();
-                for (long long x = threadIdx.x; x < seg_nnz; x += kLongThreads) p.c_val[cb + off + x] = (T)acc[x];
-            }
             off += seg_nnz;
-            __threadfence();
             __syncthreads();
         }
     }
+}
+
+// Rewinds the numeric pass's long-row counter (a kernel, so that the
+// sequence can be captured in a graph).
+__global__ void k_long_rewind(unsigned int* queue) {
+    if (threadIdx.x == 0) queue[1] = 0u;
 }
 
 }  // namespace reap

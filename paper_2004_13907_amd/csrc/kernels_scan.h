@@ -146,12 +146,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(ScanArgs s0, const 
 
 // Zeroes the counters (a kernel rather than a memset, so the sequence can be
 // captured in a graph).
-__global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long) {
+__global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long) {  // n_long[0..2]
     uint32_t* p = reinterpret_cast<uint32_t*>(ctr);
     const int64_t words = (int64_t)nprod * (int64_t)(sizeof(Counters) / 4);
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words; x += (int64_t)gridDim.x * blockDim.x)
         p[x] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *n_long = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 3) n_long[threadIdx.x] = 0u;  // count and the two queue counters
 }
 
 }  // namespace reap

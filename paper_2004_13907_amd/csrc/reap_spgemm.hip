@@ -207,7 +207,7 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, i
         return o;
     };
     const size_t o_ctr = carve((size_t)Q * sizeof(Counters));
-    const size_t o_nlong = carve(sizeof(unsigned int));
+    const size_t o_nlong = carve(4 * sizeof(unsigned int));  // long-row count, two queue counters
     const size_t o_cls = carve((size_t)R);
     const size_t o_rnnz = carve((size_t)R * 4);
     const size_t o_win = carve((size_t)R * 8);
@@ -299,6 +299,7 @@ BatchMap batch_map(const reap_spgemm_s* p) {
     bm.nprod = p->nprod;
     bm.long_list = p->long_list;
     bm.n_long = p->n_long;
+    bm.queue = p->n_long + 1;
     return bm;
 }
 
@@ -378,7 +379,7 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
                                p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
-        // the long-row count is known on the device only: a fixed grid walks the list
+        // the long-row count is known on the device only: a fixed grid takes rows from the list
         const int lgrid =
             (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * p->long_wg_per_cu));
         hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a0, P, bm);
@@ -573,9 +574,10 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
         max_group_nnz = std::max(max_group_nnz, h.max_group_nnz);
     }
 
-    // long rows: the list is walked by long_wg_per_cu workgroups per CU; FP32 output
-    // needs an FP64 accumulator per workgroup (one segment of the widest row)
-    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus * p->long_wg_per_cu));
+    // long rows: one numeric workgroup per CU (its LDS takes most of the CU's);
+    // FP32 output needs an FP64 accumulator per workgroup (one segment of the
+    // widest row)
+    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus));
     p->gvals_stride = 0;
     if (p->dtype == REAP_F32 && nl > 0) {
         const int64_t stride =
@@ -650,8 +652,10 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     ev_record(p, kPhNumHash, true);
     ev_record(p, kPhNumGroup, false);
     if (p->long_rows > 0) {
-        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->long_grid), dim3(kLongThreads), 0, p->stream, a0, P,
-                           bm);
+        hipLaunchKernelGGL(k_long_rewind, dim3(1), dim3(64), 0, p->stream, bm.queue);
+        REAP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->long_grid), dim3(kLongNumThreads), 0, p->stream, a0,
+                           P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_long_num");
     }
@@ -897,6 +901,7 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     p->th.wave_hash_products = clampi(o.wave_hash_products, 0, kWaveHashProducts, kWaveHashProducts);
     p->th.wave_small_nnz = clampi(o.wave_small_values, 0, kWaveSmallNnz, kWaveSmallNnz);
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
+    p->th.group_lds_values = clampi(o.group_lds_values, kLongMinVals, kLongVals, kLongVals);
     p->long_wg_per_cu = clampi(o.long_workgroups_per_cu, 1, 8, 2);
 
     hipError_t e = hipGetDevice(&p->device);

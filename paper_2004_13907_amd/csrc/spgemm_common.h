@@ -68,6 +68,7 @@ struct BatchMap {
     int32_t nprod;
     int2* long_list;           // [sum of rows]
     unsigned int* n_long;      // length of long_list
+    unsigned int* queue;       // next long_list entry to take: [0] symbolic, [1] numeric
 };
 
 // Thresholds of one plan (clamped to the kernel capacities above).
@@ -77,6 +78,7 @@ struct Thresholds {
     int wave_hash_products;  // <= kWaveHashProducts
     int wave_small_nnz;      // <= kWaveSmallNnz
     int group_lds_span;      // <= 32 * kGroupBitsWords, multiple of 32
+    int group_lds_values;    // FP64 LDS slots per rank chunk of a long row, kLongMinVals..kLongVals
 };
 
 }  // namespace reap

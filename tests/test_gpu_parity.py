@@ -119,6 +119,8 @@ PATHS = {
     "group_segments": {"wave_max_products": -1, "group_lds_span": 64},
     "group_segments_mixed": {"wave_max_products": 8, "group_lds_span": 96},
     "hash_tiny_wave": {"wave_max_span": 40, "wave_hash_products": 48, "wave_max_products": 200},
+    "long_chunks": {"wave_max_products": -1, "group_lds_values": 256},
+    "long_chunks_segments": {"wave_max_products": 8, "group_lds_span": 320, "group_lds_values": 256},
 }
 
 
@@ -160,6 +162,23 @@ def test_long_rows_wide_columns(reap):
     B = synth.CSR(300, n, rp.astype(np.int32), np.concatenate(cols).astype(np.int32),
                   rng.uniform(-1, 1, size=int(rp[-1])))
     check_full(reap, A, B, label="wide columns n=600000")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("order", ["sorted", "unsorted"])
+def test_long_rows_rank_chunks(reap, dtype, order):
+    """Long rows of C with more entries than the LDS accumulator holds (about
+    4800 per row against 4096 slots) and B rows of ~120 entries: with B in
+    column order the row is summed in LDS chunk by chunk, with B rows out of
+    order every product goes to device memory.  Both must agree with the
+    oracle."""
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    A = synth.erdos_renyi(400, 2000, 0.04, seed=51, dtype=npdt)
+    B = synth.random_tiny(2000, 6000, 0.02, seed=52, dtype=npdt, unsorted=(order == "unsorted"))
+    check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s" % (order, dtype))
+    check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s, 256 slots" % (order, dtype),
+               group_lds_values=256)
 
 
 # --- numerics / determinism ---------------------------------------------------
