@@ -37,22 +37,25 @@ struct LongChunk {
     double a[kWave];      // the A value
 };
 
-// Calls fn(col, bidx, a) once for every partial product of the A row
-// [rs, rs + nA) that this wavefront owns.  Wavefront w takes the chunks of 64
-// entries starting at w*64, (w + nwaves)*64, ...  Entries whose B row has 64
-// or more entries are walked by the whole wavefront, 64 consecutive B entries
-// per step.  The other entries of the chunk are taken in groups of G lanes
-// (G the smallest power of two not below the chunk's longest such B row):
-// 64/G entries per step, lane `off` of a group reads B entry b0 + off.
-// Entries whose B row has skip_from or more entries (skip_from >= 64) are
-// not visited.  CHECK sets *unsorted when a B row of 64 or more entries is not
-// in ascending column order.
+// Calls fn(col, v) once for every partial product of the A row [rs, rs + nA)
+// that this wavefront owns, v = a_ik * b_kj in FP64 (0 when !VALS).
+// Wavefront w takes the chunks of 64 entries starting at w*64,
+// (w + nwaves)*64, ...  Entries whose B row has 64 or more entries are walked
+// by the whole wavefront, 256 consecutive B entries per step (four loads of
+// column and value in flight per lane before any is used).  The other
+// entries of the chunk are taken in groups of G lanes (G the smallest power
+// of two not below the chunk's longest such B row): 64/G entries per step,
+// lane `off` of a group reads B entry b0 + off.  Entries whose B row has
+// skip_from or more entries (skip_from >= 64) are not visited.  CHECK sets
+// *unsorted when a B row of 64 or more entries is not in ascending column
+// order.
 template <typename IdxT, typename T, bool VALS, bool CHECK = false, typename Fn>
 __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int32_t* __restrict__ a_col,
                                                   const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
-                                                  const int32_t* __restrict__ b_col, int wave, int nwaves,
-                                                  LongChunk<IdxT>& tb, Fn&& fn, bool* unsorted = nullptr,
-                                                  int64_t skip_from = INT64_MAX) {
+                                                  const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
+                                                  int wave, int nwaves, LongChunk<IdxT>& tb, Fn&& fn,
+                                                  bool* unsorted = nullptr, int64_t skip_from = INT64_MAX) {
+    constexpr int U = 4;
     const int lane = lane_id();
     for (int64_t ch = (int64_t)wave * kWave; ch < nA; ch += (int64_t)nwaves * kWave) {
         const int cnt = (int)min((int64_t)kWave, nA - ch);
@@ -83,7 +86,9 @@ __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int
                 const int e = e0 + g;
                 if (e < cnt && off < tb.len[e]) {
                     const IdxT q = tb.b0[e] + (IdxT)off;
-                    fn(b_col[q], (int64_t)q, VALS ? tb.a[e] : 0.0);
+                    const int c = b_col[q];
+                    const double v = VALS ? tb.a[e] * (double)b_val[q] : 0.0;
+                    fn(c, v);
                 }
             }
             wave_sync();
@@ -95,12 +100,59 @@ __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int
             const int64_t eb0 = (int64_t)shfl(b0, e);
             const int64_t elen = shfl(len, e);
             const double ea = VALS ? shfl(a, e) : 0.0;
-            for (int64_t q = lane; q < elen; q += kWave) {
-                const int c = b_col[eb0 + q];
-                if (CHECK && q > 0 && b_col[eb0 + q - 1] > c) *unsorted = true;
-                fn(c, eb0 + q, ea);
+            int last = INT32_MIN;  // CHECK: column of the entry before this step's first
+            for (int64_t q0 = 0; q0 < elen; q0 += U * kWave) {
+                int c[U];
+                T bv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t q = q0 + u * kWave + lane;
+                    c[u] = -1;
+                    bv[u] = T(0);
+                    if (q < elen) {
+                        c[u] = b_col[eb0 + q];
+                        if (VALS) bv[u] = b_val[eb0 + q];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (CHECK) {
+                        int prev = __shfl_up(c[u], 1, kWave);
+                        if (lane == 0) prev = last;
+                        if (c[u] >= 0 && prev > c[u]) *unsorted = true;
+                        last = __shfl(c[u], kWave - 1, kWave);
+                    }
+                    if (c[u] >= 0) fn(c[u], VALS ? ea * (double)bv[u] : 0.0);
+                }
             }
         }
+    }
+}
+
+// Walks a B row stored in column order (entries [0, elen) of col/val) from
+// entry qlo, U steps of 64 entries at a time, calling fn(col, a * val) for
+// the entries with columns in [clo, chi); stops after the step in which a
+// column reaches chi or the row ends.
+template <int U, typename T, typename Fn>
+__device__ __forceinline__ void chunk_walk(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t qlo,
+                                           int64_t elen, int clo, int chi, double a, int lane, Fn&& fn) {
+    for (int64_t base = qlo; base < elen; base += U * kWave) {
+        int c[U];
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = base + u * kWave + lane;
+            c[u] = INT32_MAX;
+            v[u] = T(0);
+            if (q < elen) {
+                c[u] = col[q];
+                v[u] = val[q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= clo && c[u] < chi) fn(c[u], a * (double)v[u]);
+        if (ballot(c[U - 1] < chi) != ~0ull) break;
     }
 }
 
@@ -148,8 +200,8 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
         int64_t span = p.n;
         if (p.n > seg_cols) {
             int cmin = INT32_MAX, cmax = -1;
-            long_row_products<IdxT, float, false>(rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
-                                                  [&](int col, int64_t, double) {
+            long_row_products<IdxT, float, false>(rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, nullptr, w, kLongWaves,
+                                                  s_tb[w], [&](int col, double) {
                                                       cmin = min(cmin, col);
                                                       cmax = max(cmax, col);
                                                   });
@@ -167,8 +219,8 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             for (int x = threadIdx.x; x < seg_w; x += kLongThreads) s_bits[x] = 0u;
             __syncthreads();
             long_row_products<IdxT, float, false, true>(
-                rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, w, kLongWaves, s_tb[w],
-                [&](int col, int64_t, double) {
+                rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, nullptr, w, kLongWaves, s_tb[w],
+                [&](int col, double) {
                     if (col >= seg_lo && col < seg_hi) {
                         const int d = col - seg_lo;
                         atomicOr(&s_bits[d >> 5], 1u << (d & 31));
@@ -276,8 +328,8 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
             const int seg_hi = seg_lo + seg_w * 32;
             for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
             __syncthreads();
-            long_row_products<IdxT, T, false>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
-                                              [&](int col, int64_t, double) {
+            long_row_products<IdxT, T, false>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
+                                              [&](int col, double) {
                                                   if (col >= seg_lo && col < seg_hi) {
                                                       const int d = col - seg_lo;
                                                       atomicOr(&s_bits[d >> 5], 1u << (d & 31));
@@ -309,10 +361,10 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 // the whole segment in LDS
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) s_vals[x] = 0.0;
                 __syncthreads();
-                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
-                                                 [&](int col, int64_t bidx, double a) {
+                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
+                                                 [&](int col, double v) {
                                                      if (col >= seg_lo && col < seg_hi)
-                                                         atomicAdd(&s_vals[rank_of(col)], a * (double)p.b_val[bidx]);
+                                                         atomicAdd(&s_vals[rank_of(col)], v);
                                                  });
                 __syncthreads();
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)s_vals[x];
@@ -330,10 +382,10 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 // A entries whose B row is at least this long are walked chunk by chunk
                 const int64_t walk_from = sorted_b ? (int64_t)max(kWave, 16 * nch) : INT64_MAX;
                 long_row_products<IdxT, T, true>(
-                    rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, w, NW, s_tb[w],
-                    [&](int col, int64_t bidx, double a) {
+                    rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
+                    [&](int col, double v) {
                         if (col >= seg_lo && col < seg_hi)
-                            __hip_atomic_fetch_add(&acc[rank_of(col)], a * (double)p.b_val[bidx], __ATOMIC_RELAXED,
+                            __hip_atomic_fetch_add(&acc[rank_of(col)], v, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                     },
                     nullptr, walk_from);
@@ -399,13 +451,15 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                                         qlo = nlo;
                                     }
                                 }
-                                // walk from qlo until the chunk's column range ends
-                                for (int64_t base = qlo; base < elen; base += kWave) {
-                                    const int64_t q = base + lane;
-                                    const int col = q < elen ? p.b_col[eb0 + q] : INT32_MAX;
-                                    if (col >= clo && col < chi)
-                                        atomicAdd(&s_vals[rank_of(col) - r0], ea * (double)p.b_val[eb0 + q]);
-                                    if (ballot(col < chi) != ~0ull) break;
+                                // walk from qlo until the chunk's column range ends: four
+                                // steps of loads in flight when the B row averages 256 or
+                                // more entries per chunk, else one
+                                if (elen >= 256 * (int64_t)nch) {
+                                    chunk_walk<4>(p.b_col + eb0, p.b_val + eb0, qlo, elen, clo, chi, ea, lane,
+                                                  [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); });
+                                } else {
+                                    chunk_walk<1>(p.b_col + eb0, p.b_val + eb0, qlo, elen, clo, chi, ea, lane,
+                                                  [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); });
                                 }
                             }
                         }

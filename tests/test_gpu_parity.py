@@ -168,17 +168,19 @@ def test_long_rows_wide_columns(reap):
 @pytest.mark.parametrize("order", ["sorted", "unsorted"])
 def test_long_rows_rank_chunks(reap, dtype, order):
     """Long rows of C with more entries than the LDS accumulator holds (about
-    4800 per row against 4096 slots) and B rows of ~120 entries: with B in
-    column order the row is summed in LDS chunk by chunk, with B rows out of
-    order every product goes to device memory.  Both must agree with the
-    oracle."""
+    14000 per row against 8192 slots) and B rows of ~600 entries.  With B in
+    column order: the default slots walk every B row in two rank chunks with
+    four steps of loads in flight, 1024 slots walk them in 14 chunks one step
+    at a time, and 256 slots send every product to device-memory atomics (B
+    rows too short for 55 chunks).  With B out of order every product goes to
+    device memory.  All must agree with the oracle."""
     tdt = torch.float64 if dtype == "f64" else torch.float32
     npdt = np.float64 if dtype == "f64" else np.float32
-    A = synth.erdos_renyi(400, 2000, 0.04, seed=51, dtype=npdt)
-    B = synth.random_tiny(2000, 6000, 0.02, seed=52, dtype=npdt, unsorted=(order == "unsorted"))
-    check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s" % (order, dtype))
-    check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s, 256 slots" % (order, dtype),
-               group_lds_values=256)
+    A = synth.erdos_renyi(300, 2000, 0.02, seed=51, dtype=npdt)
+    B = synth.random_tiny(2000, 20000, 0.03, seed=52, dtype=npdt, unsorted=(order == "unsorted"))
+    for slots in (0, 1024, 256):
+        check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s, slots %d" % (order, dtype, slots),
+                   group_lds_values=slots)
 
 
 # --- numerics / determinism ---------------------------------------------------
