@@ -356,10 +356,13 @@ def run_served(args):
 
     budget = 0.6 * torch.cuda.get_device_properties(0).total_memory
 
-    def trace(n, qps, seed):
+    def trace(n, qps, seed, pick_seed=2):
+        # the saturation run and the load levels serve the same sequence of
+        # jobs (pick_seed), so that a level's rate is that fraction of the
+        # capacity measured on the same work; only the arrival times differ
+        pick = np.random.default_rng(pick_seed).integers(0, len(pool), size=n)
         rng = np.random.default_rng(seed)
         t = np.cumsum(rng.exponential(1.0 / qps, size=n)) if qps else np.zeros(n)
-        pick = rng.integers(0, len(pool), size=n)
         return [Request(i, pool[p][2], pool[p][3], float(t[i]), kind=pool[p][0]) for i, p in enumerate(pick)]
 
     def serve(reqs):
@@ -369,7 +372,7 @@ def run_served(args):
         finally:
             srv.close()
 
-    serve(trace(min(len(pool), 16), 0, 1))            # warm-up (plans, graphs of the allocator)
+    serve(trace(min(len(pool), 16), 0, 1, pick_seed=1))  # warm-up (plans, graphs of the allocator)
     sat = serve(trace(args.serve_requests, 0, 2))     # closed loop: everything queued at t = 0
     sat_qps = sat.requests / sat.seconds
     log("saturation: %.1f jobs/s, %.2f GFLOP/s" % (sat_qps, sat.gflops))

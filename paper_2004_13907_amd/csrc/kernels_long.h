@@ -276,10 +276,11 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 //  - a larger segment is cut into nch chunks of V consecutive ranks (a column
 //    range each).  If the long B rows are in column order (checked by the
 //    symbolic pass), the A entries whose B row has at least max(64, 16 nch)
-//    entries are walked chunk by chunk: a 64-way search finds where the
-//    chunk's column range starts in the B row, the wavefront walks it until
-//    the range ends, and the chunk's LDS sums are added to the segment's
-//    slots in device memory.  The products of the other A entries (short B
+//    entries are walked chunk by chunk: each lane binary-searches where the
+//    chunk's column range starts in its entry's B row; rows averaging fewer
+//    than 64 entries per chunk are then walked by their own lane, longer
+//    ones by the whole wavefront, until the range ends; the chunk's LDS sums
+//    are added to the segment's slots in device memory.  The products of the other A entries (short B
 //    rows, which a per-chunk walk would revisit too often) are added into
 //    those slots with FP64 atomics;
 //  - if a long B row is not in column order, every product of the segment is
@@ -429,38 +430,50 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                                 len = (int64_t)p.b_rp[k + 1] - (int64_t)x0;
                                 a = (double)p.a_val[rs + ch + lane];
                             }
-                            uint64_t lm = ballot(len >= walk_from);
-                            while (lm) {
-                                const int e = __ffsll((unsigned long long)lm) - 1;
-                                lm &= lm - 1;
-                                const int64_t eb0 = shfl(b0, e);
-                                const int64_t elen = shfl(len, e);
-                                const double ea = shfl(a, e);
-                                // narrow [qlo, qhi] to at most 64 entries around the first column >= clo
-                                int64_t qlo = 0, qhi = elen;
-                                while (qhi - qlo > kWave) {
-                                    const int64_t step = (qhi - qlo + kWave - 1) / kWave;
-                                    const int64_t probe = qlo + (int64_t)lane * step;
-                                    const bool below = probe < qhi && p.b_col[eb0 + probe] < clo;
-                                    const int nb = __popcll(ballot(below));  // a prefix of the probes (sorted row)
-                                    if (nb == 0) {
-                                        qhi = qlo;
+                            // every lane finds where the chunk's column range starts in
+                            // its own B row (binary search, the 64 searches side by side)
+                            const bool walk = len >= walk_from;
+                            int64_t cur = 0;
+                            {
+                                int64_t hi = walk ? len : 0;
+                                while (cur < hi) {
+                                    const int64_t mid = (cur + hi) >> 1;
+                                    if (p.b_col[b0 + mid] < clo) cur = mid + 1; else hi = mid;
+                                }
+                            }
+                            auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
+                            // B rows averaging fewer than 64 entries per chunk: each lane
+                            // walks its own row until the range ends
+                            const bool heavy = walk && len >= (int64_t)kWave * nch;
+                            bool act = walk && !heavy && cur < len;
+                            while (ballot(act)) {
+                                if (act) {
+                                    const int col = p.b_col[b0 + cur];
+                                    const T bv = p.b_val[b0 + cur];
+                                    if (col < chi) {
+                                        add(col, a * (double)bv);
+                                        ++cur;
+                                        act = cur < len;
                                     } else {
-                                        const int64_t nlo = qlo + (int64_t)(nb - 1) * step;
-                                        qhi = min(qhi, qlo + (int64_t)nb * step);
-                                        qlo = nlo;
+                                        act = false;
                                     }
                                 }
-                                // walk from qlo until the chunk's column range ends: four
-                                // steps of loads in flight when the B row averages 256 or
-                                // more entries per chunk, else one
-                                if (elen >= 256 * (int64_t)nch) {
-                                    chunk_walk<4>(p.b_col + eb0, p.b_val + eb0, qlo, elen, clo, chi, ea, lane,
-                                                  [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); });
-                                } else {
-                                    chunk_walk<1>(p.b_col + eb0, p.b_val + eb0, qlo, elen, clo, chi, ea, lane,
-                                                  [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); });
-                                }
+                            }
+                            // the others: the whole wavefront walks one row at a time, four
+                            // steps of loads in flight when the row averages 256 or more
+                            // entries per chunk, else one
+                            uint64_t hm = ballot(heavy);
+                            while (hm) {
+                                const int e = __ffsll((unsigned long long)hm) - 1;
+                                hm &= hm - 1;
+                                const int64_t eb0 = shfl(b0, e);
+                                const int64_t elen = shfl(len, e);
+                                const int64_t q0 = shfl(cur, e);
+                                const double ea = shfl(a, e);
+                                if (elen >= 256 * (int64_t)nch)
+                                    chunk_walk<4, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
+                                else
+                                    chunk_walk<1, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
                             }
                         }
                         __syncthreads();

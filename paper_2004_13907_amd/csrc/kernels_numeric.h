@@ -16,19 +16,19 @@ template <typename T, typename IdxT, typename IdxC>
 struct NumArgs {
     int64_t m;
     int64_t n;
-    const IdxT* a_rp;
-    const int32_t* a_col;
-    const T* a_val;
-    const IdxT* b_rp;
-    const int32_t* b_col;
-    const T* b_val;
-    const IdxC* c_rp;
-    int32_t* c_col;
-    T* c_val;
-    const uint8_t* cls;
-    const int2* win;
-    Counters* ctr;
-    double* gvals;          // per-workgroup FP64 accumulators of long rows with FP32 output
+    gptr<const IdxT> a_rp;
+    gptr<const int32_t> a_col;
+    gptr<const T> a_val;
+    gptr<const IdxT> b_rp;
+    gptr<const int32_t> b_col;
+    gptr<const T> b_val;
+    gptr<const IdxC> c_rp;
+    gptr<int32_t> c_col;
+    gptr<T> c_val;
+    gptr<const uint8_t> cls;
+    gptr<const int2> win;
+    gptr<Counters> ctr;
+    gptr<double> gvals;     // per-workgroup FP64 accumulators of long rows with FP32 output
     int64_t gvals_stride;   // doubles per workgroup slot
     Thresholds th;
 };

@@ -11,15 +11,15 @@ template <typename IdxT>
 struct SymArgs {
     int64_t m;                 // rows of A
     int64_t n;                 // columns of B
-    const IdxT* a_rp;
-    const int32_t* a_col;
-    const IdxT* b_rp;
-    const int32_t* b_col;
-    uint8_t* cls;              // [m] row class
-    int32_t* rnnz;             // [m] nnz of each row of C
-    int2* win;                 // [m] {lo, words} bitmap window of wavefront rows; {lo, span} of long rows
-    Counters* ctr;             // this product's counters
-    WGPart* parts;             // per-workgroup statistics of the wavefront symbolic kernel
+    gptr<const IdxT> a_rp;
+    gptr<const int32_t> a_col;
+    gptr<const IdxT> b_rp;
+    gptr<const int32_t> b_col;
+    gptr<uint8_t> cls;         // [m] row class
+    gptr<int32_t> rnnz;        // [m] nnz of each row of C
+    gptr<int2> win;            // [m] {lo, words} bitmap window of wavefront rows; {lo, span} of long rows
+    gptr<Counters> ctr;        // this product's counters
+    gptr<WGPart> parts;        // per-workgroup statistics of the wavefront symbolic kernel
     Thresholds th;
 };
 

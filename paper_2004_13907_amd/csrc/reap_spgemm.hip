@@ -441,15 +441,15 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
         SymArgs<IdxT> a{};
         a.m = ps.m;
         a.n = ps.n;
-        a.a_rp = static_cast<const IdxT*>(A[q].row_ptr);
-        a.a_col = A[q].col_idx;
-        a.b_rp = static_cast<const IdxT*>(B[q].row_ptr);
-        a.b_col = B[q].col_idx;
-        a.cls = p->cls + ps.row_off;
-        a.rnnz = p->rnnz + ps.row_off;
-        a.win = p->win + ps.row_off;
-        a.ctr = p->ctr + q;
-        a.parts = p->parts + ps.block_off;
+        a.a_rp = to_gptr(static_cast<const IdxT*>(A[q].row_ptr));
+        a.a_col = to_gptr(A[q].col_idx);
+        a.b_rp = to_gptr(static_cast<const IdxT*>(B[q].row_ptr));
+        a.b_col = to_gptr(B[q].col_idx);
+        a.cls = to_gptr(p->cls + ps.row_off);
+        a.rnnz = to_gptr(p->rnnz + ps.row_off);
+        a.win = to_gptr(p->win + ps.row_off);
+        a.ctr = to_gptr(p->ctr + q);
+        a.parts = to_gptr(p->parts + ps.block_off);
         a.th = p->th;
         ScanArgs s{};
         s.rnnz = p->rnnz + ps.row_off;
@@ -674,19 +674,19 @@ reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_cs
         NumArgs<T, IdxT, IdxC> a{};
         a.m = ps.m;
         a.n = ps.n;
-        a.a_rp = static_cast<const IdxT*>(A[q].row_ptr);
-        a.a_col = A[q].col_idx;
-        a.a_val = static_cast<const T*>(A[q].values);
-        a.b_rp = static_cast<const IdxT*>(B[q].row_ptr);
-        a.b_col = B[q].col_idx;
-        a.b_val = static_cast<const T*>(B[q].values);
-        a.c_rp = static_cast<const IdxC*>(c_row_ptr[q]);
-        a.c_col = c_col[q];
-        a.c_val = static_cast<T*>(c_val[q]);
-        a.cls = p->cls + ps.row_off;
-        a.win = p->win + ps.row_off;
-        a.ctr = p->ctr + q;
-        a.gvals = static_cast<double*>(p->gvals.base);
+        a.a_rp = to_gptr(static_cast<const IdxT*>(A[q].row_ptr));
+        a.a_col = to_gptr(A[q].col_idx);
+        a.a_val = to_gptr(static_cast<const T*>(A[q].values));
+        a.b_rp = to_gptr(static_cast<const IdxT*>(B[q].row_ptr));
+        a.b_col = to_gptr(B[q].col_idx);
+        a.b_val = to_gptr(static_cast<const T*>(B[q].values));
+        a.c_rp = to_gptr(static_cast<const IdxC*>(c_row_ptr[q]));
+        a.c_col = to_gptr(c_col[q]);
+        a.c_val = to_gptr(static_cast<T*>(c_val[q]));
+        a.cls = to_gptr(p->cls + ps.row_off);
+        a.win = to_gptr(p->win + ps.row_off);
+        a.ctr = to_gptr(p->ctr + q);
+        a.gvals = to_gptr(static_cast<double*>(p->gvals.base));
         a.gvals_stride = p->gvals_stride;
         a.th = p->th;
         std::memcpy(p->h_stage_num + (size_t)q * sizeof(a), &a, sizeof(a));

@@ -5,6 +5,24 @@
 
 namespace reap {
 
+// Pointer into device memory, typed as such for the device compiler.
+// Argument structs read from a table in memory would otherwise hold generic
+// pointers, accessed with FLAT instructions; those count against the LDS
+// counter too, so every wait for an LDS result would also wait for the loads
+// in flight.  The host pass sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+
+template <typename T>
+__host__ __device__ inline gptr<T> to_gptr(T* p) {
+    return (gptr<T>)p;
+}
+
 // Row classes, decided by the symbolic pass from the row's partial-product
 // count P_i, its number of A entries, its column window and nnz(C_i).
 enum RowClass : uint8_t {
