@@ -214,6 +214,16 @@ __device__ __forceinline__ void row_gather(const RowTable<IdxT>& tb, const RowPl
 // matrices) fall in different LDS banks.
 __device__ __forceinline__ int pad_word(int w) { return w + (w >> 5); }
 constexpr int padded_words(int n) { return n + n / 32 + 1; }
+// Row stride of a per-wavefront bitmap: padded_words rounded up to 4 words,
+// so it can be cleared with 16-byte stores.
+constexpr int bitmap_stride(int n) { return (padded_words(n) + 3) & ~3; }
+
+// Clears words [0, padded_words(nw)) of a 16-byte aligned bitmap row (and up
+// to 3 words after them, inside the row stride), four words per lane.
+__device__ __forceinline__ void clear_bitmap(uint32_t* bits, int nw) {
+    for (int x = 4 * lane_id(); x < padded_words(nw); x += 4 * kWave)
+        *reinterpret_cast<uint4*>(bits + x) = make_uint4(0u, 0u, 0u, 0u);
+}
 
 // First B index of the row (the first entry with a non-empty B row).
 template <typename IdxT>
@@ -252,7 +262,7 @@ __device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan&
     const int64_t span = (int64_t)cmax - cmin + 1;
     if (span <= th.wave_max_span) {
         const int nw = (int)((span + 31) >> 5);
-        for (int x = lane; x < padded_words(nw); x += kWave) bits[x] = 0u;
+        clear_bitmap(bits, nw);
         wave_sync();
 #pragma unroll
         for (int t = 0; t < MAXIT; ++t) {
@@ -309,7 +319,7 @@ __global__ void __launch_bounds__(kWaveKernelWaves * 64) __attribute__((amdgpu_w
 k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     constexpr int W = kWaveKernelWaves;
     constexpr int MAXIT = kWaveMaxIt;
-    __shared__ uint32_t s_bits[W][padded_words(kWaveBitsWords)];  // padded, + a dummy word
+    __shared__ __align__(16) uint32_t s_bits[W][bitmap_stride(kWaveBitsWords)];  // padded, + a dummy word
     __shared__ RowTable<IdxT> s_tb[W];
     __shared__ WaveStage<IdxT> s_stage[W];
     __shared__ WGPart s_part[W];
@@ -408,12 +418,12 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
 
 // Numeric work of one row: gather, bitmap over the window, per-word prefix
 // counts, rank each product's column, accumulate, write the sorted row.
-// Lanes without a product aim at the dummy word bp[WMAX] and the dummy slot
+// Lanes without a product aim at the dummy word bits[pad_word(WMAX)] and the dummy slot
 // vals[NCMAX], so no lane needs a branch.
 template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT>
 __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int64_t i, RowTable<IdxT>& tb,
                                             const RowPlan& pl, IdxT safe, int slot, bool has_entry, T a,
-                                            uint2* bp, double* vals, int32_t* cols_l) {
+                                            uint32_t* bits, uint32_t* pfx, double* vals, int32_t* cols_l) {
     const int lane = lane_id();
     const int nIt = uniform_i32(pl.nIt);
     bool ok[MAXIT];
@@ -426,7 +436,7 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     const int64_t cb = uniform((int64_t)p.c_rp[i]);
     const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
     if (has_entry) tb.a[slot] = (double)a;
-    for (int x = lane; x < padded_words(nw); x += kWave) bp[x] = make_uint2(0u, 0u);
+    clear_bitmap(bits, nw);
     for (int x = lane; x < nc; x += kWave) vals[x] = 0.0;
     wave_sync();
     int dd[MAXIT];
@@ -437,7 +447,7 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
         if (t < nIt) {
             const int d = ok[t] ? col[t] - lo : WMAX * 32;
             dd[t] = d;
-            atomicOr(&bp[pad_word(d >> 5)].x, 1u << (d & 31));
+            atomicOr(&bits[pad_word(d >> 5)], 1u << (d & 31));
             const int ow = min(ge0 + t, kWave - 1);
             prod[t] = tb.a[ow] * (double)bv[t];
         }
@@ -447,11 +457,11 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     const int per = (nw + kWave - 1) / kWave;
     const int w0 = min(lane * per, nw), w1 = min(w0 + per, nw);
     int local = 0;
-    for (int x = w0; x < w1; ++x) local += __popc(bp[pad_word(x)].x);
+    for (int x = w0; x < w1; ++x) local += __popc(bits[pad_word(x)]);
     int run = dpp_incl_scan(local) - local;
     for (int x = w0; x < w1; ++x) {
-        const uint32_t word = bp[pad_word(x)].x;
-        bp[pad_word(x)].y = (uint32_t)run;
+        const uint32_t word = bits[pad_word(x)];
+        pfx[pad_word(x)] = (uint32_t)run;
         run += __popc(word);
     }
     wave_sync();
@@ -459,8 +469,8 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     for (int t = 0; t < MAXIT; ++t) {
         if (t < nIt) {
             const int d = dd[t];
-            const uint2 e = bp[pad_word(d >> 5)];
-            int rk = (int)e.y + __popc(e.x & ((1u << (d & 31)) - 1u));
+            const int pw = pad_word(d >> 5);
+            int rk = (int)pfx[pw] + __popc(bits[pw] & ((1u << (d & 31)) - 1u));
             rk = (ok[t] && rk < nc) ? rk : NCMAX;  // rk < nc whenever the pattern matches the symbolic pass
             atomicAdd(&vals[rk], prod[t]);
             cols_l[rk] = d + lo;
@@ -476,13 +486,15 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
 
 // ---------------------------------------------------------------------------
 // Numeric, one wavefront per row of class `want` (bitmap window of at most WMAX
-// words, at most NCMAX entries).  The bitmap word and its prefix count share
-// one 64-bit LDS slot, so a column's rank (its position in the sorted row) is
-// one LDS read plus a popcount.
+// words, at most NCMAX entries).  The bitmap words and their prefix counts are
+// two 32-bit LDS arrays (dense words, so the bitmap ORs of a step spread over
+// the banks), and a column's rank (its position in the sorted row) is two LDS
+// reads plus a popcount.
 template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT, int W, bool TAB>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
-    __shared__ uint2 s_bp[W][padded_words(WMAX)];  // .x bitmap word, .y set bits before it (padded, + dummy)
+    __shared__ __align__(16) uint32_t s_bits[W][bitmap_stride(WMAX)];  // bitmap words (padded, + dummy)
+    __shared__ uint32_t s_pfx[W][padded_words(WMAX)];                  // set bits before each word
     __shared__ double s_vals[W][NCMAX + 1];
     __shared__ int32_t s_cols[W][NCMAX + 1];
     __shared__ RowTable<IdxT> s_tb[W];
@@ -490,7 +502,8 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    uint2* bp = s_bp[w];
+    uint32_t* bits = s_bits[w];
+    uint32_t* pfx = s_pfx[w];
     double* vals = s_vals[w];
     int32_t* cols_l = s_cols[w];
     RowTable<IdxT>& tb = s_tb[w];
@@ -519,7 +532,8 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
         int slot;
         const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot);
         const IdxT safe = row_safe_index(b0, len);
-        num_row_bmp<T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bp, vals, cols_l);
+        num_row_bmp<T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bits, pfx, vals,
+                                                       cols_l);
     }
 }
 
