@@ -90,8 +90,8 @@ typedef struct {
  *                        8192; 0 = default 8192).  A long row's window
  *                        segment whose entries fit is summed in LDS in one
  *                        walk; a larger one in chunks of this many
- *                        consecutive entries, when the long B rows it reads
- *                        are in column order, else in device memory.
+ *                        consecutive entries, when the B rows it reads are
+ *                        in column order, else in device memory.
  *   profile           -- non-zero: record per-phase device times (see
  *                        reap_spgemm_phase_times).
  *   wave_small_values -- rows of C with at most this many entries (and a

@@ -27,7 +27,7 @@ constexpr int kLongSegWords = 8192;     // 262144 columns per window segment
 constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS
 constexpr int kLongMinVals = 256;       // smallest rank chunk accepted
 constexpr int kLongMaxChunks = kLongSegWords * 32 / kLongMinVals;
-constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a long row's B row is not in column order
+constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a B row read by a long row is not in column order
 
 // Per-wavefront table of one chunk of (at most 64) A entries.
 template <typename IdxT>
@@ -45,16 +45,14 @@ struct LongChunk {
 // column and value in flight per lane before any is used).  The other
 // entries of the chunk are taken in groups of G lanes (G the smallest power
 // of two not below the chunk's longest such B row): 64/G entries per step,
-// lane `off` of a group reads B entry b0 + off.  Entries whose B row has
-// skip_from or more entries (skip_from >= 64) are not visited.  CHECK sets
-// *unsorted when a B row of 64 or more entries is not in ascending column
-// order.
+// lane `off` of a group reads B entry b0 + off.  CHECK sets *unsorted when a
+// B row is not in ascending column order.
 template <typename IdxT, typename T, bool VALS, bool CHECK = false, typename Fn>
 __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int32_t* __restrict__ a_col,
                                                   const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
                                                   const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
                                                   int wave, int nwaves, LongChunk<IdxT>& tb, Fn&& fn,
-                                                  bool* unsorted = nullptr, int64_t skip_from = INT64_MAX) {
+                                                  bool* unsorted = nullptr) {
     constexpr int U = 4;
     const int lane = lane_id();
     for (int64_t ch = (int64_t)wave * kWave; ch < nA; ch += (int64_t)nwaves * kWave) {
@@ -84,16 +82,24 @@ __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int
             const int per = kWave >> logG;
             for (int e0 = 0; e0 < cnt; e0 += per) {
                 const int e = e0 + g;
-                if (e < cnt && off < tb.len[e]) {
+                const bool on = e < cnt && off < tb.len[e];
+                int c = -1;
+                double v = 0.0;
+                if (on) {
                     const IdxT q = tb.b0[e] + (IdxT)off;
-                    const int c = b_col[q];
-                    const double v = VALS ? tb.a[e] * (double)b_val[q] : 0.0;
-                    fn(c, v);
+                    c = b_col[q];
+                    if (VALS) v = tb.a[e] * (double)b_val[q];
                 }
+                if (CHECK) {
+                    // lane - 1 holds the previous entry of the same B row when off > 0
+                    const int prev = __shfl_up(c, 1, kWave);
+                    if (on && off > 0 && prev > c) *unsorted = true;
+                }
+                if (on) fn(c, v);
             }
             wave_sync();
         }
-        uint64_t lm = ballot(lng && len < skip_from);
+        uint64_t lm = ballot(lng);
         while (lm) {
             const int e = __ffsll((unsigned long long)lm) - 1;
             lm &= lm - 1;
@@ -249,7 +255,7 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             lo = cmax >= 0 ? cmin : 0;
             span = cmax >= 0 ? (int64_t)cmax - cmin + 1 : 0;
         }
-        // the numeric pass walks long B rows of long rows in column order only
+        // the numeric pass walks the B rows of long rows in column order only
         // when they are stored that way
         if (ballot(unsorted) && lane_id() == 0) atomicOr(&p.ctr->bad_csr, kUnsortedB);
         if (threadIdx.x == 0) {
@@ -275,19 +281,14 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 //    in LDS in one walk of the products;
 //  - a larger segment is cut into nch chunks of V consecutive ranks (a column
 //    range each).  If the long B rows are in column order (checked by the
-//    symbolic pass), the A entries whose B row has at least max(64, 16 nch)
-//    entries are walked chunk by chunk: each lane binary-searches where the
-//    chunk's column range starts in its entry's B row; rows averaging fewer
-//    than 64 entries per chunk are then walked by their own lane, longer
-//    ones by the whole wavefront, until the range ends; the chunk's LDS sums
-//    are added to the segment's slots in device memory.  The products of the other A entries (short B
-//    rows, which a per-chunk walk would revisit too often) are added into
-//    those slots with FP64 atomics;
+//    symbolic pass), each chunk is summed in LDS and written to C: every lane
+//    binary-searches where the chunk's column range starts in its A entry's
+//    B row; rows averaging fewer than 64 entries per chunk are then walked by
+//    their own lane, longer ones by the whole wavefront, until the range ends;
 //  - if a long B row is not in column order, every product of the segment is
-//    added into device memory with FP64 atomics.
-// The device slots are C's own values for FP64 and a per-workgroup FP64
-// buffer for FP32 (rounded once on the copy out).  Only this workgroup
-// touches the row's slots, so those atomics are workgroup-scoped.
+//    added with FP64 atomics into device memory: C's own values for FP64, a
+//    per-workgroup FP64 buffer for FP32 (rounded once on the copy out).  Only
+//    this workgroup touches those slots, so the atomics are workgroup-scoped.
 template <typename T, typename IdxT, typename IdxC>
 __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
                                                              const NumArgs<T, IdxT, IdxC>* __restrict__ P,
@@ -369,120 +370,115 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                                                  });
                 __syncthreads();
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)s_vals[x];
+            } else if (sorted_b) {
+                // rank chunks, each summed in LDS and written to C as it completes
+                const int nch = (seg_nnz + V - 1) / V;
+                // column boundaries of the chunks: chunk c holds ranks [cV, cV + V),
+                // columns [s_bound[c], s_bound[c + 1])
+                if (threadIdx.x == 0) {
+                    s_bound[0] = seg_lo;
+                    s_bound[nch] = seg_hi;
+                }
+                for (int x = w0; x < w1; ++x) {
+                    const int r0 = (int)s_pfx[x];
+                    const uint32_t bw = s_bits[x];
+                    const int c = __popc(bw);
+                    // every multiple of V in [r0, r0 + c) but 0
+                    for (int k = max(1, (r0 + V - 1) / V); k * V < r0 + c; ++k) {
+                        uint32_t m = bw;
+                        for (int t = k * V - r0; t > 0; --t) m &= m - 1;  // drop the lower set bits
+                        s_bound[k] = seg_lo + x * 32 + (__ffs(m) - 1);
+                    }
+                }
+                __syncthreads();
+                for (int c = 0; c < nch; ++c) {
+                    const int clo = s_bound[c], chi = s_bound[c + 1];
+                    const int r0 = c * V, rn = min(V, seg_nnz - r0);
+                    for (int x = threadIdx.x; x < rn; x += NT) s_vals[x] = 0.0;
+                    __syncthreads();
+                    auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
+                    for (int64_t ch = (int64_t)w * kWave; ch < nA; ch += (int64_t)NW * kWave) {
+                        const int cnt = (int)min((int64_t)kWave, nA - ch);
+                        int64_t b0 = 0, len = 0;
+                        double a = 0.0;
+                        if (lane < cnt) {
+                            const int k = p.a_col[rs + ch + lane];
+                            const IdxT x0 = p.b_rp[k];
+                            b0 = (int64_t)x0;
+                            len = (int64_t)p.b_rp[k + 1] - (int64_t)x0;
+                            a = (double)p.a_val[rs + ch + lane];
+                        }
+                        // every lane finds where the chunk's column range starts in its
+                        // own B row (binary search, the 64 searches side by side)
+                        int64_t cur = 0;
+                        {
+                            int64_t hi = len;
+                            while (cur < hi) {
+                                const int64_t mid = (cur + hi) >> 1;
+                                if (p.b_col[b0 + mid] < clo) cur = mid + 1; else hi = mid;
+                            }
+                        }
+                        // B rows averaging fewer than 64 entries per chunk: each lane
+                        // walks its own row until the range ends
+                        const bool heavy = len >= (int64_t)kWave * nch;
+                        bool act = !heavy && cur < len;
+                        while (ballot(act)) {
+                            if (act) {
+                                const int col = p.b_col[b0 + cur];
+                                const T bv = p.b_val[b0 + cur];
+                                if (col < chi) {
+                                    add(col, a * (double)bv);
+                                    ++cur;
+                                    act = cur < len;
+                                } else {
+                                    act = false;
+                                }
+                            }
+                        }
+                        // the others: the whole wavefront walks one row at a time, four
+                        // steps of loads in flight when the row averages 256 or more
+                        // entries per chunk, else one
+                        uint64_t hm = ballot(heavy);
+                        while (hm) {
+                            const int e = __ffsll((unsigned long long)hm) - 1;
+                            hm &= hm - 1;
+                            const int64_t eb0 = shfl(b0, e);
+                            const int64_t elen = shfl(len, e);
+                            const int64_t q0 = shfl(cur, e);
+                            const double ea = shfl(a, e);
+                            if (elen >= 256 * (int64_t)nch)
+                                chunk_walk<4, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
+                            else
+                                chunk_walk<1, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
+                        }
+                    }
+                    __syncthreads();
+                    for (int x = threadIdx.x; x < rn; x += NT) p.c_val[cb + off + r0 + x] = (T)s_vals[x];
+                    __syncthreads();
+                }
             } else {
+                // a long B row out of column order: every product into device memory
                 double* acc;
                 if constexpr (sizeof(T) == sizeof(double)) {
-                    acc = reinterpret_cast<double*>(p.c_val) + cb + off;
+                    acc = (double*)(p.c_val + cb + off);
                 } else {
                     acc = p.gvals + (int64_t)blockIdx.x * p.gvals_stride;
                 }
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) acc[x] = 0.0;
                 __threadfence_block();
                 __syncthreads();
-                const int nch = (seg_nnz + V - 1) / V;
-                // A entries whose B row is at least this long are walked chunk by chunk
-                const int64_t walk_from = sorted_b ? (int64_t)max(kWave, 16 * nch) : INT64_MAX;
-                long_row_products<IdxT, T, true>(
-                    rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
-                    [&](int col, double v) {
-                        if (col >= seg_lo && col < seg_hi)
-                            __hip_atomic_fetch_add(&acc[rank_of(col)], v, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                    },
-                    nullptr, walk_from);
-                if (sorted_b) {
-                    // column boundaries of the rank chunks: chunk c holds ranks
-                    // [cV, cV + V), columns [s_bound[c], s_bound[c + 1])
-                    if (threadIdx.x == 0) {
-                        s_bound[0] = seg_lo;
-                        s_bound[nch] = seg_hi;
-                    }
-                    for (int x = w0; x < w1; ++x) {
-                        const int r0 = (int)s_pfx[x];
-                        const uint32_t bw = s_bits[x];
-                        const int c = __popc(bw);
-                        // every multiple of V in [r0, r0 + c) but 0
-                        for (int k = max(1, (r0 + V - 1) / V); k * V < r0 + c; ++k) {
-                            uint32_t m = bw;
-                            for (int t = k * V - r0; t > 0; --t) m &= m - 1;  // drop the lower set bits
-                            s_bound[k] = seg_lo + x * 32 + (__ffs(m) - 1);
-                        }
-                    }
-                    // the atomics of every thread are done before the merges read the
-                    // slots (all of the workgroup's accesses go through one CU, so a
+                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
+                                                 [&](int col, double v) {
+                                                     if (col >= seg_lo && col < seg_hi)
+                                                         __hip_atomic_fetch_add(&acc[rank_of(col)], v,
+                                                                                __ATOMIC_RELAXED,
+                                                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                                                 });
+                if constexpr (sizeof(T) != sizeof(double)) {
+                    // the adds of every wavefront are complete before the buffer is read
+                    // back (all of the workgroup's accesses go through one CU, so a
                     // workgroup-scope fence is enough: an agent-scope one would write
                     // back and invalidate the whole L2 of the XCD, per row)
-                    __threadfence_block();
-                    __syncthreads();
-                    for (int c = 0; c < nch; ++c) {
-                        const int clo = s_bound[c], chi = s_bound[c + 1];
-                        const int r0 = c * V, rn = min(V, seg_nnz - r0);
-                        for (int x = threadIdx.x; x < rn; x += NT) s_vals[x] = 0.0;
-                        __syncthreads();
-                        for (int64_t ch = (int64_t)w * kWave; ch < nA; ch += (int64_t)NW * kWave) {
-                            const int cnt = (int)min((int64_t)kWave, nA - ch);
-                            int64_t b0 = 0, len = 0;
-                            double a = 0.0;
-                            if (lane < cnt) {
-                                const int k = p.a_col[rs + ch + lane];
-                                const IdxT x0 = p.b_rp[k];
-                                b0 = (int64_t)x0;
-                                len = (int64_t)p.b_rp[k + 1] - (int64_t)x0;
-                                a = (double)p.a_val[rs + ch + lane];
-                            }
-                            // every lane finds where the chunk's column range starts in
-                            // its own B row (binary search, the 64 searches side by side)
-                            const bool walk = len >= walk_from;
-                            int64_t cur = 0;
-                            {
-                                int64_t hi = walk ? len : 0;
-                                while (cur < hi) {
-                                    const int64_t mid = (cur + hi) >> 1;
-                                    if (p.b_col[b0 + mid] < clo) cur = mid + 1; else hi = mid;
-                                }
-                            }
-                            auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
-                            // B rows averaging fewer than 64 entries per chunk: each lane
-                            // walks its own row until the range ends
-                            const bool heavy = walk && len >= (int64_t)kWave * nch;
-                            bool act = walk && !heavy && cur < len;
-                            while (ballot(act)) {
-                                if (act) {
-                                    const int col = p.b_col[b0 + cur];
-                                    const T bv = p.b_val[b0 + cur];
-                                    if (col < chi) {
-                                        add(col, a * (double)bv);
-                                        ++cur;
-                                        act = cur < len;
-                                    } else {
-                                        act = false;
-                                    }
-                                }
-                            }
-                            // the others: the whole wavefront walks one row at a time, four
-                            // steps of loads in flight when the row averages 256 or more
-                            // entries per chunk, else one
-                            uint64_t hm = ballot(heavy);
-                            while (hm) {
-                                const int e = __ffsll((unsigned long long)hm) - 1;
-                                hm &= hm - 1;
-                                const int64_t eb0 = shfl(b0, e);
-                                const int64_t elen = shfl(len, e);
-                                const int64_t q0 = shfl(cur, e);
-                                const double ea = shfl(a, e);
-                                if (elen >= 256 * (int64_t)nch)
-                                    chunk_walk<4, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
-                                else
-                                    chunk_walk<1, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
-                            }
-                        }
-                        __syncthreads();
-                        for (int x = threadIdx.x; x < rn; x += NT) acc[r0 + x] += s_vals[x];
-                        __syncthreads();
-                    }
-                }
-                if constexpr (sizeof(T) != sizeof(double)) {
-                    // the adds of every wavefront are complete before the buffer is read back
                     __threadfence_block();
                     __syncthreads();
                     for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)acc[x];

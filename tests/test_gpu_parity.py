@@ -183,6 +183,21 @@ def test_long_rows_rank_chunks(reap, dtype, order):
                    group_lds_values=slots)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_long_rows_unsorted_short_b(reap, dtype):
+    """Long rows whose B rows are all short (~40 entries) and out of column
+    order: a chunk walk would need them sorted, so the symbolic pass must flag
+    them and the chunked segments (1024 slots, ~6600 entries per row) must
+    take the device-memory path."""
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    A = synth.erdos_renyi(300, 2000, 0.1, seed=53, dtype=npdt)
+    B = synth.random_tiny(2000, 20000, 0.002, seed=54, dtype=npdt, unsorted=True)
+    for slots in (0, 1024):
+        check_full(reap, A, B, dtype=tdt, label="unsorted short B, %s, slots %d" % (dtype, slots),
+                   group_lds_values=slots)
+
+
 # --- numerics / determinism ---------------------------------------------------
 
 def test_integer_values_bit_exact(reap):
