@@ -425,7 +425,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="batched: skip the one-product-at-a-time comparison")
     ap.add_argument("--serve-pool", type=int, default=32, help="served: distinct jobs (operand sets) in the pool")
     ap.add_argument("--serve-requests", type=int, default=240, help="served: requests per load level")
-    ap.add_argument("--serve-slots", type=int, default=4, help="served: concurrent batches (streams)")
+    ap.add_argument("--serve-slots", type=int, default=2, help="served: concurrent batches (streams)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = 2 if args.workload == "batched" else 20
