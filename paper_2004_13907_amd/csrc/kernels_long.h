@@ -419,20 +419,34 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                             }
                         }
                         // B rows averaging fewer than 64 entries per chunk: each lane
-                        // walks its own row until the range ends
+                        // walks its own row until the range ends, four entries per
+                        // step (their loads issued together; in a sorted row the
+                        // entries below chi are a prefix of the four)
                         const bool heavy = len >= (int64_t)kWave * nch;
                         bool act = !heavy && cur < len;
                         while (ballot(act)) {
                             if (act) {
-                                const int col = p.b_col[b0 + cur];
-                                const T bv = p.b_val[b0 + cur];
-                                if (col < chi) {
-                                    add(col, a * (double)bv);
-                                    ++cur;
-                                    act = cur < len;
-                                } else {
-                                    act = false;
+                                int c4[4];
+                                T v4[4];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    c4[u] = INT32_MAX;
+                                    v4[u] = T(0);
+                                    if (cur + u < len) {
+                                        c4[u] = p.b_col[b0 + cur + u];
+                                        v4[u] = p.b_val[b0 + cur + u];
+                                    }
                                 }
+                                int taken = 0;
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    if (c4[u] < chi) {
+                                        add(c4[u], a * (double)v4[u]);
+                                        ++taken;
+                                    }
+                                }
+                                cur += taken;
+                                act = taken == 4 && cur < len;
                             }
                         }
                         // the others: the whole wavefront walks one row at a time, four
