@@ -449,9 +449,9 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                                 act = taken == 4 && cur < len;
                             }
                         }
-                        // the others: the whole wavefront walks one row at a time, four
-                        // steps of loads in flight when the row averages 256 or more
-                        // entries per chunk, else one
+                        // the others: the whole wavefront walks one row at a time, with
+                        // four, two or one 64-entry steps of loads in flight as the row
+                        // averages >= 256, >= 128 or fewer entries per chunk
                         uint64_t hm = ballot(heavy);
                         while (hm) {
                             const int e = __ffsll((unsigned long long)hm) - 1;
@@ -462,6 +462,8 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                             const double ea = shfl(a, e);
                             if (elen >= 256 * (int64_t)nch)
                                 chunk_walk<4, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
+                            else if (elen >= 128 * (int64_t)nch)
+                                chunk_walk<2, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
                             else
                                 chunk_walk<1, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
                         }
