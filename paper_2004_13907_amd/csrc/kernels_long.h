@@ -80,22 +80,34 @@ __device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int
             const int g = lane >> logG;
             const int off = lane & ((1 << logG) - 1);
             const int per = kWave >> logG;
-            for (int e0 = 0; e0 < cnt; e0 += per) {
-                const int e = e0 + g;
-                const bool on = e < cnt && off < tb.len[e];
-                int c = -1;
-                double v = 0.0;
-                if (on) {
-                    const IdxT q = tb.b0[e] + (IdxT)off;
-                    c = b_col[q];
-                    if (VALS) v = tb.a[e] * (double)b_val[q];
+            // two steps per trip: the loads of both are issued before either is used
+            for (int e0 = 0; e0 < cnt; e0 += 2 * per) {
+                int c[2];
+                T bv[2];
+                bool on[2];
+                int ei[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * per + g;
+                    ei[u] = e;
+                    on[u] = e < cnt && off < tb.len[e];
+                    c[u] = -1;
+                    bv[u] = T(0);
+                    if (on[u]) {
+                        const IdxT q = tb.b0[e] + (IdxT)off;
+                        c[u] = b_col[q];
+                        if (VALS) bv[u] = b_val[q];
+                    }
                 }
-                if (CHECK) {
-                    // lane - 1 holds the previous entry of the same B row when off > 0
-                    const int prev = __shfl_up(c, 1, kWave);
-                    if (on && off > 0 && prev > c) *unsorted = true;
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (CHECK) {
+                        // lane - 1 holds the previous entry of the same B row when off > 0
+                        const int prev = __shfl_up(c[u], 1, kWave);
+                        if (on[u] && off > 0 && prev > c[u]) *unsorted = true;
+                    }
+                    if (on[u]) fn(c[u], VALS ? tb.a[ei[u]] * (double)bv[u] : 0.0);
                 }
-                if (on) fn(c, v);
             }
             wave_sync();
         }
