@@ -233,21 +233,27 @@ def test_repeat_pattern_identical(reap):
 
 # --- symbolic-plan reuse: numeric-only re-multiply with new values ------------
 
-@pytest.mark.parametrize("case", ["stencil", "uniform_random_f32"])
+@pytest.mark.parametrize("case", ["stencil", "uniform_random_f32", "rank_chunks_f64"])
 def test_plan_reuse_new_values(reap, case):
     """One symbolic pass, then numeric passes over operands with the same
     patterns and fresh values (the re-multiply of an iterative method): every
     result against the oracle on those values."""
+    opts = {}
     if case == "stencil":
         A = synth.stencil27(9)
         tdt, npdt = torch.float64, np.float64
+    elif case == "rank_chunks_f64":
+        # every row long (~5600 products) and summed in six rank chunks of 256 slots
+        A = synth.erdos_renyi(1500, 1500, 0.05, seed=63)
+        tdt, npdt = torch.float64, np.float64
+        opts = {"group_lds_values": 256}
     else:
         A = synth.erdos_renyi(1500, 1500, 0.02, seed=61, dtype=np.float32)
         tdt, npdt = torch.float32, np.float32
     say("plan reuse", case)
     rng = np.random.default_rng(62)
     dA = reap.DeviceCSR.from_host(A, dtype=tdt)
-    with reap.Plan(tdt) as plan:
+    with reap.Plan(tdt, **opts) as plan:
         rp_d, nnz, _ = plan.symbolic(dA, dA)
         for it in range(3):
             vals = A.val if it == 0 else rng.uniform(-1, 1, size=A.nnz).astype(npdt)
