@@ -1,6 +1,6 @@
 """Autotuner for batched products: times candidate launch parameters (bin
 thresholds, hash-table admission, long-row column segment, workgroups per CU
-for the long rows) on a sample of the batch and keeps the fastest per
+of the long-row symbolic pass) on a sample of the batch and keeps the fastest per
 workload signature in a JSON cache.  Every candidate computes the same result
 (thresholds only decide which kernel handles a row); the tuner measures, it
 never changes the arithmetic."""
