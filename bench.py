@@ -40,7 +40,7 @@ WORKLOADS = {
                "density U[1e-3, 1e-2] per product, FP64, CSR int32 operands, int64 C row pointers; run in waves "
                "whose C fits the HBM budget, each wave one batched call (graph-captured passes)",
     "served": "open-loop Poisson arrivals of jobs drawn 40/40/20 from stencil27 g in [16, 64] (A*A, FP64), R-MAT "
-              "scale 12-18 (A*A^T, FP32) and uniform-random m lognormal in [1024, 65536], d in [1e-3, 1e-2] (FP64); "
+              "scale 13-18 (A*A^T, FP32; scale 12 of the named 12-18 range left out) and uniform-random m lognormal in [1024, 65536], d in [1e-3, 1e-2] (FP64); "
               "operands resident on the device; continuous batching on 4 streams, admission by the symbolic "
               "pass's exact footprint",
 }
@@ -94,9 +94,24 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, products, budget_s: float):
-    """The oracle (never tuned) on the host cores, on the whole workload,
-    repeated until about budget_s seconds of work; median time."""
+    """The oracle (never tuned) on the host cores: all usable cores on the
+    whole workload, repeated until about budget_s seconds of work (median),
+    and one thread -- the single-thread CPU reference point of the paper's
+    evaluation -- on the whole workload when that fits the same budget, else
+    on an evenly spaced sample of rows scaled by its products."""
+    import numpy as np
     import oracle
     cores = len(os.sched_getaffinity(0))
     threads = max(1, min(cores, oracle.max_threads() if os.environ.get("OMP_NUM_THREADS") else cores))
@@ -110,9 +125,25 @@ def cpu_baseline(A, B, products, budget_s: float):
             break
     times.sort()
     med = times[len(times) // 2]
+    # one thread: the whole workload if it fits the budget, else every k-th row
+    est_single = med * threads
+    if est_single <= budget_s:
+        rows, sample = None, "whole workload"
+        sprods = products
+    else:
+        k = int(np.ceil(est_single / budget_s))
+        rows = np.arange(0, A.rows, k, dtype=np.int64)
+        sprods = int(oracle.spgemm(A, B, rows=rows, threads=threads, with_values=False).total_products)
+        sample = "every %d-th row (%d rows, %d partial products)" % (k, rows.size, sprods)
+    t0 = time.perf_counter()
+    oracle.spgemm(A, B, rows=rows, threads=1)
+    t1 = time.perf_counter() - t0
     return {"value": round(2.0 * products / med / 1e9, 4), "unit": "GFLOP/s", "cores": threads,
             "kind": "oracle",
-            "sample": "whole workload (all rows), %d repetitions, median %.3f s" % (len(times), med)}
+            "sample": "whole workload (all rows), %d repetitions, median %.3f s" % (len(times), med),
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(2.0 * sprods / t1 / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+                              "sample": "%s, one run, %.3f s" % (sample, t1)}}
 
 
 def calib_copy(gib: float = 1.0, reps: int = 5):

@@ -107,6 +107,11 @@ typedef struct {
  *   long_workgroups_per_cu -- workgroups per compute unit that take rows
  *                        from the long-row list in the symbolic pass (1..8;
  *                        0 = default 2; the numeric pass runs one per CU).
+ *   test_fail_alloc   -- test hook for callers' error handling: when n > 0,
+ *                        the plan's n-th device allocation (workspace,
+ *                        accumulators or transpose scratch, counted from 1)
+ *                        fails as if the device were out of memory, so the
+ *                        call returns REAP_ERR_OUT_OF_MEMORY; 0 = never.
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -120,10 +125,15 @@ typedef struct {
     int32_t wave_small_values;
     int32_t graph;
     int32_t long_workgroups_per_cu;
-    int32_t reserved[6];
+    int32_t test_fail_alloc;
+    int32_t reserved[5];
 } reap_options_t;
 
-/* Per-class row counts of the last symbolic pass (how rows were binned). */
+/*
+ * Per-class row counts of the last symbolic pass (how rows were binned) and,
+ * once a numeric call has followed it, how the long rows' window segments
+ * were accumulated (summed over the numeric calls since that symbolic call).
+ */
 typedef struct {
     int64_t empty;        /* rows with no partial product */
     int64_t wave_bitmap;  /* one wavefront, LDS bitmap over the column window */
@@ -131,6 +141,9 @@ typedef struct {
     int64_t group;        /* one workgroup (long rows), LDS or device bitmap */
     int64_t max_row_products;
     int64_t max_row_nnz;
+    int64_t long_segments_lds;      /* long-row window segments summed in LDS in one walk */
+    int64_t long_segments_chunked;  /* ... summed in LDS rank chunks (B rows in column order) */
+    int64_t long_segments_device;   /* ... summed with device-memory atomics */
 } reap_bin_stats_t;
 
 /*
@@ -202,6 +215,20 @@ reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t plan, int64_t count, const
                                         int32_t* const* c_col_idx, void* const* c_values);
 
 /*
+ * Device memory the plan will hold once a (batched) symbolic call on these
+ * operands has returned: its workspace, which only grows, plus the FP32
+ * long-row accumulators counted at their largest (one window segment of the
+ * widest B per compute unit).  A caller that admits work by its device
+ * footprint adds this to C's arrays before calling symbolic (the serving
+ * loop's admission, the analog of the paper's coarse-grained overlap of
+ * CPU and accelerator work in Section II).  count, A, B as in
+ * reap_spgemm_batch_symbolic (count = 1 for one product).  Host-only: no
+ * device work, no allocation.  Errors: INVALID_ARG.
+ */
+reap_status_t reap_spgemm_workspace_query(reap_spgemm_t plan, int64_t count, const reap_csr_t* A,
+                                          const reap_csr_t* B, size_t* bytes);
+
+/*
  * Device transpose: T = A^T in CSR (A's compressed-column form), so that a
  * product A * A^T needs only A on the device.  T has A.cols rows and A.cols
  * + 1 row pointers of A's row-pointer type (t_row_ptr, device); t_col_idx
@@ -221,7 +248,11 @@ reap_status_t reap_csr_transpose(reap_spgemm_t plan, const reap_csr_t* A, void* 
 /* Release the plan's workspace and the plan (NULL is accepted). */
 reap_status_t reap_spgemm_destroy(reap_spgemm_t plan);
 
-/* Row classes of the last symbolic pass.  Errors: INVALID_ARG, STATE. */
+/*
+ * Row classes of the last symbolic pass and, after a numeric call, the long-row
+ * segment counts (reading those synchronises the plan's stream).
+ * Errors: INVALID_ARG, STATE, HIP.
+ */
 reap_status_t reap_spgemm_bin_stats(reap_spgemm_t plan, reap_bin_stats_t* out);
 
 /*

@@ -32,6 +32,7 @@ __all__ = [
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
+    "reap_spgemm_workspace_query",
     "reap_csr_transpose",
     "transpose",
     "reap_spgemm_destroy",
@@ -204,6 +205,21 @@ def reap_spgemm_batch_numeric(plan, As, Bs, c_row_ptrs, c_cols, c_vals) -> int:
     return lib.reap_spgemm_batch_numeric(plan, n, a, b, rp, cc, cv)
 
 
+def reap_spgemm_workspace_query(plan, As, Bs) -> int:
+    """Device bytes the plan will hold after a (batched) symbolic call on
+    these operands (raises on an invalid batch)."""
+    n = len(As)
+    if len(Bs) != n:
+        raise ValueError("A and B lists differ in length")
+    a = (reap_csr_t * n)(*[x.c_struct() for x in As])
+    b = (reap_csr_t * n)(*[x.c_struct() for x in Bs])
+    out = ctypes.c_size_t(0)
+    st = _capi.load().reap_spgemm_workspace_query(plan, n, a, b, ctypes.byref(out))
+    if st != REAP_OK:
+        raise SpGEMMError(st, "reap_spgemm_workspace_query")
+    return int(out.value)
+
+
 def reap_csr_transpose(plan, A: DeviceCSR, t_row_ptr: torch.Tensor, t_col: torch.Tensor, t_val: torch.Tensor) -> int:
     lib = _capi.load()
     a = A.c_struct()
@@ -335,6 +351,11 @@ class Batch:
 
     def _ctx(self):
         return torch.cuda.stream(self.stream) if self.stream is not None else _NullCtx()
+
+    def workspace_query(self, As, Bs) -> int:
+        """Device bytes the batch's plan will hold once symbolic(As, Bs) has
+        returned (host-only; nothing is allocated)."""
+        return reap_spgemm_workspace_query(self.plan.handle, As, Bs)
 
     def symbolic(self, As, Bs, fresh: bool = False):
         """Per-product nnz(C_q); row pointers are written on the device, into

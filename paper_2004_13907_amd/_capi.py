@@ -28,6 +28,7 @@ EXPORTED = (
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
+    "reap_spgemm_workspace_query",
     "reap_csr_transpose",
     "reap_spgemm_destroy",
     "reap_spgemm_bin_stats",
@@ -62,7 +63,8 @@ class reap_options_t(ctypes.Structure):
         ("wave_small_values", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("long_workgroups_per_cu", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("test_fail_alloc", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -74,6 +76,9 @@ class reap_bin_stats_t(ctypes.Structure):
         ("group", ctypes.c_int64),
         ("max_row_products", ctypes.c_int64),
         ("max_row_nnz", ctypes.c_int64),
+        ("long_segments_lds", ctypes.c_int64),
+        ("long_segments_chunked", ctypes.c_int64),
+        ("long_segments_device", ctypes.c_int64),
     ]
 
 
@@ -109,6 +114,9 @@ def load():
     lib.reap_spgemm_batch_numeric.argtypes = [P, ctypes.c_int64, ctypes.POINTER(reap_csr_t),
                                               ctypes.POINTER(reap_csr_t), PP, PP, PP]
     lib.reap_spgemm_batch_numeric.restype = st
+    lib.reap_spgemm_workspace_query.argtypes = [P, ctypes.c_int64, ctypes.POINTER(reap_csr_t),
+                                                ctypes.POINTER(reap_csr_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.reap_spgemm_workspace_query.restype = st
     lib.reap_csr_transpose.argtypes = [P, ctypes.POINTER(reap_csr_t), P, P, P]
     lib.reap_csr_transpose.restype = st
     lib.reap_spgemm_destroy.argtypes = [P]

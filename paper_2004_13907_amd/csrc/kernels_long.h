@@ -371,6 +371,8 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 const int x = d >> 5;
                 return (int)s_pfx[x] + __popc(s_bits[x] & ((1u << (d & 31)) - 1u));
             };
+            if (threadIdx.x == 0)
+                atomicAdd(seg_nnz <= V ? &p.ctr->seg_lds : (sorted_b ? &p.ctr->seg_chunked : &p.ctr->seg_device), 1u);
             if (seg_nnz <= V) {
                 // the whole segment in LDS
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) s_vals[x] = 0.0;

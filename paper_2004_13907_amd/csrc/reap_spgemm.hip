@@ -67,6 +67,8 @@ struct reap_spgemm_s {
     bool use_graph = false;   // capture each pass into a HIP graph, replay while the shape repeats
     bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
     int long_wg_per_cu = 2;   // workgroups per CU walking the long-row list
+    int fail_alloc_at = 0;    // test hook: the n-th device allocation of the plan fails (0 = never)
+    int alloc_count = 0;      // device allocations attempted by the plan
 
     Workspace ws;      // counters, per-row arrays, tables
     Workspace gvals;   // long-row FP64 accumulators (FP32 output only)
@@ -100,6 +102,7 @@ struct reap_spgemm_s {
 
     // state of the last symbolic call
     bool have_symbolic = false;
+    bool numeric_ran = false;          // a numeric call was enqueued since the last symbolic call
     int nprod = 0;
     std::vector<ProdState> prods;
     reap_index_t in_idx = REAP_I32;
@@ -163,6 +166,48 @@ void release_graphs(reap_spgemm_s* p) {
     p->g_num_key.clear();
 }
 
+// Device allocation of the plan's own memory; the test hook makes the n-th
+// attempt fail as an out-of-memory condition would.
+hipError_t dev_malloc(reap_spgemm_s* p, void** ptr, size_t bytes) {
+    ++p->alloc_count;
+    if (p->fail_alloc_at > 0 && p->alloc_count == p->fail_alloc_at) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
+}
+
+// Offsets of the workspace slices for R rows, Bk wavefront-kernel
+// workgroups, Tl scan tiles and Q products (256-byte aligned).
+struct WsLayout {
+    size_t o_ctr, o_nlong, o_cls, o_rnnz, o_win, o_long, o_parts, o_tiles, o_bs, o_ts, o_sa, o_na, o_sc, total;
+};
+
+WsLayout ws_layout(int64_t R, int32_t Bk, int32_t Tl, int64_t Q) {
+    WsLayout L{};
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.o_ctr = carve((size_t)Q * sizeof(Counters));
+    L.o_nlong = carve(4 * sizeof(unsigned int));  // long-row count, two queue counters
+    L.o_cls = carve((size_t)R);
+    L.o_rnnz = carve((size_t)R * 4);
+    L.o_win = carve((size_t)R * 8);
+    L.o_long = carve((size_t)R * 8);
+    L.o_parts = carve((size_t)Bk * sizeof(WGPart));
+    L.o_tiles = carve((size_t)Tl * 8);
+    L.o_bs = carve((size_t)(Q + 1) * 4);
+    L.o_ts = carve((size_t)(Q + 1) * 4);
+    L.o_sa = carve((size_t)Q * kArgBytes);
+    L.o_na = carve((size_t)Q * kArgBytes);
+    L.o_sc = carve((size_t)Q * sizeof(ScanArgs));
+    L.total = off;
+    return L;
+}
+
 // Pinned staging and counter mirror for `nprod` products.
 reap_status_t ensure_host(reap_spgemm_s* p, int nprod) {
     if ((size_t)nprod <= p->stage_cap && p->h_ctr) return REAP_OK;
@@ -200,25 +245,7 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, i
     const int32_t Bk = std::max({blocks, p->cap_blocks, 1});
     const int32_t Tl = std::max({tiles, p->cap_tiles, 1});
     const int64_t Q = std::max<int64_t>({(int64_t)nprod, p->cap_prods, 1});
-    size_t off = 0;
-    auto carve = [&](size_t bytes) {
-        size_t o = off;
-        off = align_up(off + bytes, 256);
-        return o;
-    };
-    const size_t o_ctr = carve((size_t)Q * sizeof(Counters));
-    const size_t o_nlong = carve(4 * sizeof(unsigned int));  // long-row count, two queue counters
-    const size_t o_cls = carve((size_t)R);
-    const size_t o_rnnz = carve((size_t)R * 4);
-    const size_t o_win = carve((size_t)R * 8);
-    const size_t o_long = carve((size_t)R * 8);
-    const size_t o_parts = carve((size_t)Bk * sizeof(WGPart));
-    const size_t o_tiles = carve((size_t)Tl * 8);
-    const size_t o_bs = carve((size_t)(Q + 1) * 4);
-    const size_t o_ts = carve((size_t)(Q + 1) * 4);
-    const size_t o_sa = carve((size_t)Q * kArgBytes);
-    const size_t o_na = carve((size_t)Q * kArgBytes);
-    const size_t o_sc = carve((size_t)Q * sizeof(ScanArgs));
+    const WsLayout L = ws_layout(R, Bk, Tl, Q);
     (void)hipStreamSynchronize(p->stream);
     release_graphs(p);
     if (p->ws.base) {
@@ -227,7 +254,7 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, i
         p->ws.bytes = 0;
     }
     void* base = nullptr;
-    if (hipMalloc(&base, off) != hipSuccess) {
+    if (dev_malloc(p, &base, L.total) != hipSuccess) {
         (void)hipGetLastError();
         p->cap_rows = -1;
         p->cap_blocks = p->cap_tiles = 0;
@@ -236,20 +263,20 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, i
     }
     char* b = static_cast<char*>(base);
     p->ws.base = base;
-    p->ws.bytes = off;
-    p->ctr = reinterpret_cast<Counters*>(b + o_ctr);
-    p->n_long = reinterpret_cast<unsigned int*>(b + o_nlong);
-    p->cls = reinterpret_cast<uint8_t*>(b + o_cls);
-    p->rnnz = reinterpret_cast<int32_t*>(b + o_rnnz);
-    p->win = reinterpret_cast<int2*>(b + o_win);
-    p->long_list = reinterpret_cast<int2*>(b + o_long);
-    p->parts = reinterpret_cast<WGPart*>(b + o_parts);
-    p->tiles = reinterpret_cast<long long*>(b + o_tiles);
-    p->blk_start = reinterpret_cast<int32_t*>(b + o_bs);
-    p->tile_start = reinterpret_cast<int32_t*>(b + o_ts);
-    p->sym_args = b + o_sa;
-    p->num_args = b + o_na;
-    p->scan_args = reinterpret_cast<ScanArgs*>(b + o_sc);
+    p->ws.bytes = L.total;
+    p->ctr = reinterpret_cast<Counters*>(b + L.o_ctr);
+    p->n_long = reinterpret_cast<unsigned int*>(b + L.o_nlong);
+    p->cls = reinterpret_cast<uint8_t*>(b + L.o_cls);
+    p->rnnz = reinterpret_cast<int32_t*>(b + L.o_rnnz);
+    p->win = reinterpret_cast<int2*>(b + L.o_win);
+    p->long_list = reinterpret_cast<int2*>(b + L.o_long);
+    p->parts = reinterpret_cast<WGPart*>(b + L.o_parts);
+    p->tiles = reinterpret_cast<long long*>(b + L.o_tiles);
+    p->blk_start = reinterpret_cast<int32_t*>(b + L.o_bs);
+    p->tile_start = reinterpret_cast<int32_t*>(b + L.o_ts);
+    p->sym_args = b + L.o_sa;
+    p->num_args = b + L.o_na;
+    p->scan_args = reinterpret_cast<ScanArgs*>(b + L.o_sc);
     p->cap_rows = R;
     p->cap_blocks = Bk;
     p->cap_tiles = Tl;
@@ -498,24 +525,50 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
     return run_pass(p, p->g_sym, p->g_sym_key, key, [&]() { return launch_symbolic<IdxT>(p, a0, s0); });
 }
 
-reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
-                             void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes) {
-    if (!p || count < 1 || count > INT32_MAX / 2 || !A || !B || !c_row_ptr || !c_nnz) return REAP_ERR_INVALID_ARG;
+// Shape checks of a batch and its totals (rows, wavefront-kernel
+// workgroups, scan tiles, widest B).
+struct BatchTotals {
+    int64_t rows = 0, blocks = 0, tiles = 0, max_n = 0;
+};
+
+reap_status_t batch_totals(int64_t count, const reap_csr_t* A, const reap_csr_t* B, BatchTotals* t) {
+    if (count < 1 || count > INT32_MAX / 2 || !A || !B) return REAP_ERR_INVALID_ARG;
     reap_status_t st;
     const reap_index_t in_idx = A[0].row_ptr_type;
-    int64_t rows = 0, blocks = 0, tiles = 0;
     for (int64_t q = 0; q < count; ++q) {
         if ((st = check_csr(&A[q])) != REAP_OK) return st;
         if ((st = check_csr(&B[q])) != REAP_OK) return st;
         if (A[q].cols != B[q].rows) return REAP_ERR_INVALID_ARG;
         if (A[q].row_ptr_type != in_idx || B[q].row_ptr_type != in_idx) return REAP_ERR_INVALID_ARG;
         if (A[q].rows > INT32_MAX - 1) return REAP_ERR_INVALID_ARG;  // row ids are stored as int32
-        if (!c_row_ptr[q]) return REAP_ERR_INVALID_ARG;
-        rows += A[q].rows;
-        blocks += (A[q].rows + kRowsPerBlock - 1) / kRowsPerBlock;
-        tiles += (A[q].rows + kScanTile - 1) / kScanTile;
+        t->rows += A[q].rows;
+        t->blocks += (A[q].rows + kRowsPerBlock - 1) / kRowsPerBlock;
+        t->tiles += (A[q].rows + kScanTile - 1) / kScanTile;
+        t->max_n = std::max(t->max_n, B[q].cols);
     }
-    if (rows > INT32_MAX || blocks > INT32_MAX || tiles > INT32_MAX) return REAP_ERR_INVALID_ARG;
+    if (t->rows > INT32_MAX || t->blocks > INT32_MAX || t->tiles > INT32_MAX) return REAP_ERR_INVALID_ARG;
+    return REAP_OK;
+}
+
+// Device bytes of the FP32 long-row accumulators at their largest: one
+// segment of the widest row per numeric long-row workgroup.
+size_t gvals_bound(const reap_spgemm_s* p, const BatchTotals& t) {
+    if (p->dtype != REAP_F32) return 0;
+    const int64_t stride = std::max<int64_t>(1, std::min<int64_t>(t.max_n, (int64_t)p->th.group_lds_span));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(t.rows, (int64_t)p->num_cus));
+    return (size_t)stride * (size_t)grid * sizeof(double);
+}
+
+reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                             void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes) {
+    if (!p || count < 1 || count > INT32_MAX / 2 || !A || !B || !c_row_ptr || !c_nnz) return REAP_ERR_INVALID_ARG;
+    reap_status_t st;
+    const reap_index_t in_idx = A[0].row_ptr_type;
+    BatchTotals bt;
+    if ((st = batch_totals(count, A, B, &bt)) != REAP_OK) return st;
+    for (int64_t q = 0; q < count; ++q)
+        if (!c_row_ptr[q]) return REAP_ERR_INVALID_ARG;
+    const int64_t rows = bt.rows, blocks = bt.blocks, tiles = bt.tiles;
     p->have_symbolic = false;
     if (p->ev_num_upload && p->num_upload_recorded) (void)hipEventSynchronize(p->ev_num_upload);
     if ((st = ensure_host(p, (int)count)) != REAP_OK) return st;
@@ -593,7 +646,7 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
             if (p->gvals.base) (void)hipFree(p->gvals.base);
             p->gvals.base = nullptr;
             p->gvals.bytes = 0;
-            if (hipMalloc(&p->gvals.base, need) != hipSuccess) {
+            if (dev_malloc(p, &p->gvals.base, need) != hipSuccess) {
                 (void)hipGetLastError();
                 return REAP_ERR_OUT_OF_MEMORY;
             }
@@ -604,6 +657,7 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     if (workspace_bytes) *workspace_bytes = p->ws.bytes + p->gvals.bytes;
     if (overflow) return REAP_ERR_INDEX_OVERFLOW;
     p->have_symbolic = true;
+    p->numeric_ran = false;
     return REAP_OK;
 }
 
@@ -726,6 +780,7 @@ reap_status_t numeric_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A
     }
     if (total_nnz == 0) return REAP_OK;
     const bool i32 = p->in_idx == REAP_I32, c32 = p->cidx == REAP_I32;
+    p->numeric_ran = true;
     if (p->dtype == REAP_F64) {
         if (i32 && c32) return numeric_typed<double, int32_t, int32_t>(p, A, B, c_row_ptr, c_col, c_val);
         if (i32 && !c32) return numeric_typed<double, int32_t, int64_t>(p, A, B, c_row_ptr, c_col, c_val);
@@ -793,7 +848,7 @@ reap_status_t transpose_typed(reap_spgemm_s* p, const reap_csr_t* A, void* t_row
         if (p->tws.base) (void)hipFree(p->tws.base);
         p->tws.base = nullptr;
         p->tws.bytes = 0;
-        if (hipMalloc(&p->tws.base, off) != hipSuccess) {
+        if (dev_malloc(p, &p->tws.base, off) != hipSuccess) {
             (void)hipGetLastError();
             return REAP_ERR_OUT_OF_MEMORY;
         }
@@ -903,6 +958,7 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
     p->th.group_lds_values = clampi(o.group_lds_values, kLongMinVals, kLongVals, kLongVals);
     p->long_wg_per_cu = clampi(o.long_workgroups_per_cu, 1, 8, 2);
+    p->fail_alloc_at = std::max(0, o.test_fail_alloc);
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -972,6 +1028,22 @@ reap_status_t reap_spgemm_batch_numeric(reap_spgemm_t p, int64_t count, const re
     return numeric_batch(p, count, A, B, c_row_ptr, c_col_idx, c_values);
 }
 
+reap_status_t reap_spgemm_workspace_query(reap_spgemm_t p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
+                                          size_t* bytes) {
+    if (!p || !bytes) return REAP_ERR_INVALID_ARG;
+    BatchTotals bt;
+    const reap_status_t st = batch_totals(count, A, B, &bt);
+    if (st != REAP_OK) return st;
+    // the workspace grows to the larger of its current and the needed sizes, never shrinks
+    const int64_t R = std::max<int64_t>({bt.rows, p->cap_rows, 1});
+    const int32_t Bk = std::max({(int32_t)bt.blocks, p->cap_blocks, 1});
+    const int32_t Tl = std::max({(int32_t)bt.tiles, p->cap_tiles, 1});
+    const int64_t Q = std::max<int64_t>({count, p->cap_prods, 1});
+    const size_t ws = std::max(p->ws.bytes, ws_layout(R, Bk, Tl, Q).total);
+    *bytes = ws + std::max(p->gvals.bytes, gvals_bound(p, bt));
+    return REAP_OK;
+}
+
 reap_status_t reap_csr_transpose(reap_spgemm_t p, const reap_csr_t* A, void* t_row_ptr, int32_t* t_col_idx,
                                  void* t_values) {
     if (!p || !A || !t_row_ptr) return REAP_ERR_INVALID_ARG;
@@ -997,6 +1069,17 @@ reap_status_t reap_spgemm_bin_stats(reap_spgemm_t p, reap_bin_stats_t* out) {
     out->group = (int64_t)h.cls[kClsGroup];
     out->max_row_products = (int64_t)h.max_prod;
     out->max_row_nnz = (int64_t)h.max_nnz;
+    out->long_segments_lds = out->long_segments_chunked = out->long_segments_device = 0;
+    if (p->numeric_ran && p->long_rows > 0) {
+        // the numeric kernels count on the device: wait for them and read back
+        REAP_HIP(hipStreamSynchronize(p->stream));
+        REAP_HIP(hipMemcpy(p->h_ctr, p->ctr, (size_t)p->nprod * sizeof(Counters), hipMemcpyDeviceToHost));
+        for (int q = 0; q < p->nprod; ++q) {
+            out->long_segments_lds += p->h_ctr[q].seg_lds;
+            out->long_segments_chunked += p->h_ctr[q].seg_chunked;
+            out->long_segments_device += p->h_ctr[q].seg_device;
+        }
+    }
     return REAP_OK;
 }
 

@@ -65,11 +65,12 @@ struct Counters {
     unsigned int max_prod;         // max partial products in one row (saturating)
     unsigned int max_nnz;          // max nnz of one row of C
     unsigned int n_group;          // length of the long-row list
-    unsigned int unused0;
-    unsigned int unused1;
+    unsigned int seg_lds;          // numeric: long-row window segments summed in LDS in one walk
+    unsigned int seg_chunked;      // numeric: segments summed in LDS rank chunks
     unsigned int max_group_nnz;    // max nnz of a long row
     unsigned int bad_csr;          // validation flags (bit 0: A, bit 1: B)
-    unsigned int pad[5];
+    unsigned int seg_device;       // numeric: segments summed with device-memory atomics
+    unsigned int pad[4];
 };
 
 // Rows handled by one workgroup of the wavefront kernels (4 wavefronts of

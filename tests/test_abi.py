@@ -64,7 +64,7 @@ def test_struct_layout_matches_header():
     from paper_2004_13907_amd import _capi
     assert ctypes.sizeof(_capi.reap_csr_t) == 8 * 3 + 8 + 8 * 3
     assert ctypes.sizeof(_capi.reap_options_t) == 16 * 4
-    assert ctypes.sizeof(_capi.reap_bin_stats_t) == 6 * 8
+    assert ctypes.sizeof(_capi.reap_bin_stats_t) == 9 * 8
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
@@ -73,3 +73,22 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "_lib", None)
     with pytest.raises(RuntimeError):
         _capi.load()
+
+
+def test_create_without_a_device_fails_cleanly(lib):
+    """With no GPU visible, create returns REAP_ERR_HIP, leaves the handle
+    NULL, and destroy(NULL) is accepted (the CPU tier's view of the plan's
+    error path; allocation failures are forced by the test_fail_alloc hook in
+    the GPU tests)."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    from paper_2004_13907_amd import _capi
+    h = ctypes.c_void_p()
+    opts = _capi.reap_options_t()
+    opts.test_fail_alloc = 1
+    st = lib.reap_spgemm_create(ctypes.byref(h), _capi.REAP_F64, _capi.REAP_I32, None, ctypes.byref(opts))
+    assert st == _capi.REAP_ERR_HIP and not h.value
+    assert lib.reap_spgemm_destroy(None) == _capi.REAP_OK
+    size = ctypes.c_size_t(0)
+    assert lib.reap_spgemm_workspace_query(None, 1, None, None, ctypes.byref(size)) == _capi.REAP_ERR_INVALID_ARG

@@ -41,21 +41,36 @@ def _threads():
     return max(1, min(16, oracle.max_threads()))
 
 
-def run_gpu(reap, A, B, dtype=torch.float64, index_dtype=None, c_index=None, **opts):
+def run_gpu(reap, A, B, dtype=torch.float64, index_dtype=None, c_index=None, stats=None, **opts):
+    """C = A*B through one plan; ``stats`` (a dict) receives the plan's bin
+    statistics after the numeric pass."""
     dA = reap.DeviceCSR.from_host(A, dtype=dtype, index_dtype=index_dtype)
     dB = dA if B is A else reap.DeviceCSR.from_host(B, dtype=dtype, index_dtype=index_dtype)
-    C = reap.spgemm(dA, dB, c_index_dtype=c_index, **opts)
-    torch.cuda.synchronize()
-    return C
+    with reap.Plan(dtype, c_index or torch.int32, **opts) as plan:
+        rp, nnz, _ = plan.symbolic(dA, dB)
+        col, val = plan.numeric(dA, dB, rp)
+        torch.cuda.synchronize()
+        if stats is not None:
+            stats.update(plan.bin_stats())
+    return reap.DeviceCSR(A.rows, B.cols, rp, col, val)
 
 
-def check_full(reap, A, B, dtype=torch.float64, label="", **kw):
+def check_full(reap, A, B, dtype=torch.float64, label="", expect=None, **kw):
+    """Whole-product parity; ``expect(stats)`` asserts how the rows were
+    binned and how long-row segments were summed, so that a forced path is
+    shown to have run."""
     say(label, "shape", A.rows, A.cols, B.cols, "nnz", A.nnz, B.nnz, kw)
-    C = run_gpu(reap, A, B, dtype=dtype, **kw)
+    stats = {}
+    C = run_gpu(reap, A, B, dtype=dtype, stats=stats, **kw)
     rp, col, val = C.to_host()
     ref = oracle.spgemm(A, B, threads=_threads())
     npdt = np.float64 if dtype == torch.float64 else np.float32
     assert val.dtype == npdt
+    nonempty = int(np.count_nonzero(ref.products))
+    assert stats["empty"] + stats["wave_bitmap"] + stats["wave_hash"] + stats["group"] == A.rows
+    assert stats["empty"] == A.rows - nonempty, "%s: empty-row count" % label
+    if expect is not None:
+        assert expect(stats), "%s: rows did not take the expected path: %s" % (label, stats)
     return compare_full(ref, rp, col, val, npdt, label), ref
 
 
@@ -84,12 +99,17 @@ def test_stencil_fp32(reap):
     check_full(reap, A, A, dtype=torch.float32, label="stencil g=13 fp32")
 
 
+def _all_long(st):
+    return st["wave_bitmap"] == 0 and st["wave_hash"] == 0 and st["group"] > 0
+
+
 def test_long_rows_forced_stencil(reap):
     """Every row through the long-row kernels (one and several column segments)."""
     A = synth.stencil27(7)
-    check_full(reap, A, A, label="stencil g=7, all rows long", wave_max_products=-1)
+    check_full(reap, A, A, label="stencil g=7, all rows long", wave_max_products=-1,
+               expect=lambda st: _all_long(st) and st["long_segments_lds"] == st["group"])
     check_full(reap, A, A, label="stencil g=7, all rows long, 96-column segments", wave_max_products=-1,
-               group_lds_span=96)
+               group_lds_span=96, expect=lambda st: _all_long(st) and st["long_segments_lds"] > st["group"])
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -123,13 +143,37 @@ PATHS = {
     "long_chunks_segments": {"wave_max_products": 8, "group_lds_span": 320, "group_lds_values": 256},
 }
 
+# What each forced path must show in the plan's statistics (rows per class,
+# long-row segments per accumulation method) on every input it is run on.
+PATH_EXPECT = {
+    "default": lambda st: True,
+    "all_group": _all_long,
+    "hash": lambda st: st["wave_bitmap"] == 0,
+    "small_cap": lambda st: st["wave_bitmap"] == 0 and st["group"] > 0,
+    "group_segments": lambda st: _all_long(st) and st["long_segments_lds"] + st["long_segments_chunked"]
+    + st["long_segments_device"] > st["group"],
+    "group_segments_mixed": lambda st: st["group"] > 0 and st["long_segments_lds"] + st["long_segments_chunked"]
+    + st["long_segments_device"] >= st["group"],
+    "hash_tiny_wave": lambda st: st["group"] > 0,
+    "long_chunks": lambda st: _all_long(st),
+    "long_chunks_segments": lambda st: st["group"] > 0,
+}
+# paths whose effect must show on the light irregular pairs (seed 2 and the
+# sparse pair: rows of a few dozen to a few hundred products; a hash row
+# needs a window wider than the bitmap limit and few products)
+PATH_EXPECT_IRREGULAR = {
+    "hash": lambda st: st["wave_hash"] > 0,
+    "hash_tiny_wave": lambda st: st["wave_hash"] > 0,
+}
 
-def _irregular_pair(seed, dtype=np.float64, dup=False, unsorted=False):
+
+def _irregular_pair(seed, dtype=np.float64, dup=False, unsorted=False, densities=None):
     rng = np.random.default_rng(seed)
     m, k, n = 700 + seed, 450 + 3 * seed, 900 + 7 * seed
-    A = synth.random_tiny(m, k, float(rng.uniform(0.002, 0.05)), seed=seed * 3 + 1, dtype=dtype,
+    da, db = densities if densities else (float(rng.uniform(0.002, 0.05)), float(rng.uniform(0.002, 0.06)))
+    A = synth.random_tiny(m, k, da, seed=seed * 3 + 1, dtype=dtype,
                           allow_duplicates=dup, unsorted=unsorted, empty_rows=0.1)
-    B = synth.random_tiny(k, n, float(rng.uniform(0.002, 0.06)), seed=seed * 3 + 2, dtype=dtype,
+    B = synth.random_tiny(k, n, db, seed=seed * 3 + 2, dtype=dtype,
                           allow_duplicates=dup, unsorted=unsorted, empty_rows=0.1)
     return A, B
 
@@ -139,14 +183,27 @@ def _irregular_pair(seed, dtype=np.float64, dup=False, unsorted=False):
 def test_forced_paths(reap, path, dtype):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     npdt = np.float64 if dtype == "f64" else np.float32
-    for seed in (1, 2):
-        A, B = _irregular_pair(seed, dtype=npdt, dup=(seed == 2), unsorted=(seed == 2))
-        check_full(reap, A, B, dtype=tdt, label="%s/%s seed %d" % (path, dtype, seed), **PATHS[path])
+    base = PATH_EXPECT[path]
+    irr = PATH_EXPECT_IRREGULAR.get(path, lambda st: True)
+    for seed in (1, 2, 3):
+        # seed 1 dense (products per row 300..900), seed 2 with duplicates and
+        # unsorted columns, seed 3 sparse (tens of products per row)
+        A, B = _irregular_pair(seed, dtype=npdt, dup=(seed == 2), unsorted=(seed == 2),
+                               densities=(0.01, 0.02) if seed == 3 else None)
+        if seed == 1:
+            # rows of C up to ~660 entries: 256 LDS slots must cut them into rank chunks
+            chunks = {"long_chunks": lambda st: st["long_segments_chunked"] > 0}.get(path, lambda st: True)
+            want = lambda st: base(st) and chunks(st)  # noqa: E731
+        else:
+            want = lambda st: base(st) and irr(st)  # noqa: E731
+        check_full(reap, A, B, dtype=tdt, label="%s/%s seed %d" % (path, dtype, seed), expect=want,
+                   **PATHS[path])
     # a row-skewed product (R-MAT) and a banded one (stencil) through the same path
     Rv = synth.rmat(10).astype(npdt)
-    check_full(reap, Rv, synth.transpose(Rv), dtype=tdt, label="%s/%s rmat10" % (path, dtype), **PATHS[path])
+    check_full(reap, Rv, synth.transpose(Rv), dtype=tdt, label="%s/%s rmat10" % (path, dtype), expect=base,
+               **PATHS[path])
     S = synth.stencil27(7).astype(npdt)
-    check_full(reap, S, S, dtype=tdt, label="%s/%s stencil7" % (path, dtype), **PATHS[path])
+    check_full(reap, S, S, dtype=tdt, label="%s/%s stencil7" % (path, dtype), expect=base, **PATHS[path])
 
 
 def test_long_rows_wide_columns(reap):
@@ -179,8 +236,12 @@ def test_long_rows_rank_chunks(reap, dtype, order):
     A = synth.erdos_renyi(300, 2000, 0.02, seed=51, dtype=npdt)
     B = synth.random_tiny(2000, 20000, 0.03, seed=52, dtype=npdt, unsorted=(order == "unsorted"))
     for slots in (0, 1024, 256):
+        if order == "unsorted":
+            want = lambda st: st["long_segments_device"] > 0 and st["long_segments_chunked"] == 0  # noqa: E731
+        else:
+            want = lambda st: st["long_segments_chunked"] > 0 and st["long_segments_device"] == 0  # noqa: E731
         check_full(reap, A, B, dtype=tdt, label="rank chunks %s B, %s, slots %d" % (order, dtype, slots),
-                   group_lds_values=slots)
+                   group_lds_values=slots, expect=want)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -195,7 +256,8 @@ def test_long_rows_unsorted_short_b(reap, dtype):
     B = synth.random_tiny(2000, 20000, 0.002, seed=54, dtype=npdt, unsorted=True)
     for slots in (0, 1024):
         check_full(reap, A, B, dtype=tdt, label="unsorted short B, %s, slots %d" % (dtype, slots),
-                   group_lds_values=slots)
+                   group_lds_values=slots,
+                   expect=lambda st: st["group"] > 0 and (slots == 0 or st["long_segments_device"] > 0))
 
 
 # --- numerics / determinism ---------------------------------------------------
@@ -359,6 +421,56 @@ def test_errors(reap):
             plan.symbolic(dU, W)
 
 
+def test_allocation_failure_is_reported(reap):
+    """The test hook fails the plan's n-th device allocation: the call returns
+    REAP_ERR_OUT_OF_MEMORY, a numeric call then reports STATE, the plan stays
+    destroyable, and the next symbolic call (a later allocation) succeeds and
+    gives the oracle's result."""
+    from paper_2004_13907_amd import _capi
+    U = synth.uniform_rows(300, 300, 5, seed=11)
+    dU = reap.DeviceCSR.from_host(U)
+    say("allocation failure: workspace")
+    plan = reap.Plan(torch.float64, test_fail_alloc=1)
+    try:
+        rp = torch.empty(U.rows + 1, dtype=torch.int32, device="cuda")
+        st, _, _, _ = reap.reap_spgemm_symbolic(plan.handle, dU, dU, rp)
+        assert st == _capi.REAP_ERR_OUT_OF_MEMORY
+        st = reap.reap_spgemm_numeric(plan.handle, dU, dU, rp, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                                      torch.zeros(1, dtype=torch.float64, device="cuda"))
+        assert st == _capi.REAP_ERR_STATE
+        rp, nnz, _ = plan.symbolic(dU, dU)          # second allocation: succeeds
+        col, val = plan.numeric(dU, dU, rp)
+        torch.cuda.synchronize()
+        compare_full(oracle.spgemm(U, U), rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), np.float64,
+                     "after an allocation failure")
+    finally:
+        assert reap.reap_spgemm_destroy(plan.handle) == _capi.REAP_OK
+        plan.handle = None
+    say("allocation failure: FP32 long-row accumulators")
+    R = synth.rmat(9, seed=3).astype(np.float32)
+    Rt = synth.transpose(R)
+    dR = reap.DeviceCSR.from_host(R, dtype=torch.float32)
+    dRt = reap.DeviceCSR.from_host(Rt, dtype=torch.float32)
+    with reap.Plan(torch.float32, test_fail_alloc=2) as plan:
+        with pytest.raises(reap.SpGEMMError) as e:
+            plan.symbolic(dR, dRt)
+        assert e.value.status == _capi.REAP_ERR_OUT_OF_MEMORY
+        rp, nnz, _ = plan.symbolic(dR, dRt)
+        col, val = plan.numeric(dR, dRt, rp)
+        torch.cuda.synchronize()
+        assert plan.bin_stats()["group"] > 0
+        compare_full(oracle.spgemm(R, Rt), rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), np.float32,
+                     "FP32 long rows after an allocation failure")
+    say("allocation failure: transpose scratch")
+    with reap.Plan(torch.float32, test_fail_alloc=1) as plan:
+        with pytest.raises(reap.SpGEMMError) as e:
+            reap.transpose(dR, plan=plan)
+        assert e.value.status == _capi.REAP_ERR_OUT_OF_MEMORY
+        T = reap.transpose(dR, plan=plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(T.col.cpu().numpy(), Rt.col)
+
+
 def test_index_overflow(reap):
     """An outer product of two 46341-long vectors has 46341^2 > 2^31-1 entries:
     an int32 C row pointer must be refused, an int64 one must hold nnz(C)."""
@@ -381,34 +493,124 @@ def test_index_overflow(reap):
         assert r[-1] == n * n and r[1] == n and r[n // 2] == (n // 2) * n
 
 
+# --- numeric past 2^31 entries of C ------------------------------------------------
+
+def _past_int32_operands():
+    """A (m x 1000, one entry per row in column i mod 1000) times B (1000 x
+    100000): row i of C is B's row (i mod 1000) scaled by a_i.  B rows
+    0..949 hold 60 columns inside a 20000-column window (wavefront bitmap
+    rows), rows 950..998 hold 40 columns spread over all 100000 (wavefront
+    hash rows), row 999 holds 300 (a long row).  With m = 37,000,000 C has
+    about 2.19e9 entries, so its last rows lie past offset 2^31."""
+    rng = np.random.default_rng(231)
+    k, n, m = 1000, 100_000, 37_000_000
+    brows = []
+    for j in range(k):
+        if j < 950:
+            lo = int(rng.integers(0, n - 20_000))
+            brows.append(np.sort(rng.choice(20_000, size=60, replace=False)) + lo)
+        elif j < 999:
+            brows.append(np.sort(rng.choice(n, size=40, replace=False)))
+        else:
+            brows.append(np.sort(rng.choice(n, size=300, replace=False)))
+    blen = np.array([r.size for r in brows], dtype=np.int64)
+    brp = np.zeros(k + 1, dtype=np.int64)
+    np.cumsum(blen, out=brp[1:])
+    B = synth.CSR(k, n, brp.astype(np.int32), np.concatenate(brows).astype(np.int32),
+                  rng.uniform(-1, 1, size=int(brp[-1])))
+    acol = (np.arange(m, dtype=np.int64) % k).astype(np.int32)
+    A = synth.CSR(m, k, np.arange(m + 1, dtype=np.int32), acol, rng.uniform(0.5, 2.0, size=m))
+    return A, B, blen
+
+
+def test_numeric_past_int32_offsets(reap):
+    """C with about 2.19e9 entries (int64 row pointer): the whole row pointer
+    against its closed form, column and value checksums over every entry, and
+    rows lying past offset 2^31 (every class: wavefront bitmap, wavefront
+    hash, long) entry by entry against the oracle."""
+    A, B, blen = _past_int32_operands()
+    say("numeric past 2^31: A %d x %d, B %d x %d" % (A.rows, A.cols, B.rows, B.cols))
+    dA = reap.DeviceCSR.from_host(A)
+    dB = reap.DeviceCSR.from_host(B)
+    with reap.Plan(torch.float64, torch.int64) as plan:
+        rp_d, nnz, prods = plan.symbolic(dA, dB)
+        stats = plan.bin_stats()
+        col_d, val_d = plan.numeric(dA, dB, rp_d)
+        torch.cuda.synchronize()
+    row_len = blen[A.col.astype(np.int64)]
+    assert nnz == int(row_len.sum()) == prods and nnz > 2**31
+    assert stats["wave_bitmap"] > 0 and stats["wave_hash"] > 0 and stats["group"] > 0, stats
+    rp = rp_d.cpu().numpy()
+    exp_rp = np.zeros(A.rows + 1, dtype=np.int64)
+    np.cumsum(row_len, out=exp_rp[1:])
+    assert np.array_equal(rp, exp_rp), "row pointer differs from its closed form"
+    # checksums over every entry: sum of columns (exact in int64), sum of values
+    colsum_b = np.add.reduceat(B.col.astype(np.int64), B.row_ptr[:-1].astype(np.int64))
+    valsum_b = np.add.reduceat(B.val, B.row_ptr[:-1].astype(np.int64))
+    k_of = A.col.astype(np.int64)
+    assert int(torch.sum(col_d, dtype=torch.int64).item()) == int(colsum_b[k_of].sum())
+    gsum = float(torch.sum(val_d).item())
+    esum = float(np.sum(A.val * valsum_b[k_of]))
+    bound = float(np.sum(np.abs(A.val) * np.add.reduceat(np.abs(B.val), B.row_ptr[:-1].astype(np.int64))[k_of]))
+    assert abs(gsum - esum) <= 1e-9 * bound, (gsum, esum)
+    # rows past 2^31, entry by entry: every class, the straddling row, the last rows
+    first_past = int(np.searchsorted(exp_rp, 2**31, side="right")) - 1
+    tail = np.arange(first_past, A.rows)
+    rng = np.random.default_rng(7)
+    pick = [first_past, A.rows - 1]
+    for cls_rows in (tail[(tail % 1000) < 950], tail[((tail % 1000) >= 950) & ((tail % 1000) < 999)],
+                     tail[(tail % 1000) == 999]):
+        pick.extend(rng.choice(cls_rows, size=min(400, cls_rows.size), replace=False).tolist())
+    rows = np.unique(np.asarray(pick, dtype=np.int64))
+    ref = oracle.spgemm(A, B, rows=rows, threads=_threads())
+    idx = np.concatenate([np.arange(rp[i], rp[i + 1]) for i in rows])
+    assert idx.min() < 2**31 <= idx.max()
+    sel = torch.from_numpy(idx).to(col_d.device)
+    gcol = col_d.index_select(0, sel).cpu().numpy()
+    gval = val_d.index_select(0, sel).cpu().numpy()
+    del col_d, val_d, rp_d
+    local_rp = np.zeros(rows.size + 1, dtype=np.int64)
+    np.cumsum(rp[rows + 1] - rp[rows], out=local_rp[1:])
+    compare_rows(ref, np.arange(rows.size), local_rp, gcol, gval, np.float64, "rows past 2^31")
+
+
 # --- full-size skewed product (last: the largest case) ----------------------------
 
-def test_rmat_full_size_sampled(reap):
-    """R-MAT scale 18, A*A^T in FP32: the whole row pointer against the
-    oracle's pattern pass, values on the heaviest rows plus a random sample."""
+def test_rmat_full_size(reap):
+    """R-MAT scale 18, A*A^T in FP32, every entry: the whole row pointer and
+    product count against the oracle's pattern pass, then columns and values
+    of all 1.28e9 entries compared block by block (oracle row blocks of about
+    equal nnz against the matching slices of the GPU result)."""
     A = synth.rmat(18)
     B = synth.transpose(A)
-    say("rmat 18 A*A^T fp32 (sampled rows)")
+    say("rmat 18 A*A^T fp32 (every entry, streamed in row blocks)")
     dA = reap.DeviceCSR.from_host(A, dtype=torch.float32)
     dB = reap.DeviceCSR.from_host(B, dtype=torch.float32)
     with reap.Plan(torch.float32) as plan:
         rp_d, nnz, prods = plan.symbolic(dA, dB)
         col_d, val_d = plan.numeric(dA, dB, rp_d)
+        torch.cuda.synchronize()
         stats = plan.bin_stats()
-    torch.cuda.synchronize()
     rp = rp_d.cpu().numpy().astype(np.int64)
     pat = oracle.spgemm(A, B, threads=_threads(), with_values=False)
     assert np.array_equal(rp, pat.row_ptr)
     assert prods == pat.total_products
     assert stats["max_row_products"] == int(pat.products.max())
-    rng = np.random.default_rng(18)
-    heavy = np.argsort(np.diff(pat.row_ptr))[-24:]
-    rows = np.unique(np.concatenate([heavy, rng.choice(A.rows, 1500, replace=False)]))
-    ref = oracle.spgemm(A, B, rows=rows, threads=_threads())
-    idx = np.concatenate([np.arange(rp[i], rp[i + 1]) for i in rows])
-    sel = torch.from_numpy(idx).to(col_d.device)
-    gcol = col_d.index_select(0, sel).cpu().numpy()
-    gval = val_d.index_select(0, sel).cpu().numpy()
-    local_rp = np.zeros(rows.size + 1, dtype=np.int64)
-    np.cumsum(rp[rows + 1] - rp[rows], out=local_rp[1:])
-    compare_rows(ref, np.arange(rows.size), local_rp, gcol, gval, np.float32, "rmat18 sampled")
+    nblocks = 16
+    cuts = np.searchsorted(rp, np.linspace(0, nnz, nblocks + 1)[1:-1])
+    bounds = np.unique(np.concatenate([[0], cuts, [A.rows]]))
+    checked = 0
+    worst = 0.0
+    for r0, r1 in zip(bounds[:-1], bounds[1:]):
+        rows = np.arange(r0, r1, dtype=np.int64)
+        ref = oracle.spgemm(A, B, rows=rows, threads=_threads())
+        e0, e1 = int(rp[r0]), int(rp[r1])
+        gcol = col_d[e0:e1].cpu().numpy()
+        gval = val_d[e0:e1].cpu().numpy()
+        res = compare_full(ref, rp[r0:r1 + 1] - rp[r0], gcol, gval, np.float32,
+                           "rmat18 rows %d..%d" % (r0, r1))
+        checked += res["entries"]
+        worst = max(worst, res["max_err"])
+        del ref, gcol, gval
+    assert checked == nnz
+    say("rmat 18: %d entries compared, max scaled error %.2e" % (checked, worst))

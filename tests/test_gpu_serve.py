@@ -28,16 +28,18 @@ def reap():
     return r
 
 
-def _pool(reap):
-    """(kind, host A, host B, device A, device B) for a small mix of jobs."""
+def _pool(reap, served_sizes=False):
+    """(kind, host A, host B, device A, device B) for a small mix of jobs; with
+    ``served_sizes`` the mix also holds jobs at the served workload's sizes
+    (stencil g = 16, R-MAT scales 13 and 14, uniform-random m = 4096)."""
     jobs = []
-    for g in (6, 9, 12):
+    for g in (6, 9, 12) + ((16,) if served_sizes else ()):
         S = synth.stencil27(g, seed=g)
         jobs.append(("stencil", S, S, torch.float64))
-    for sc in (8, 9, 10):
+    for sc in (8, 9, 10) + ((13, 14) if served_sizes else ()):
         R = synth.rmat(sc, seed=sc).astype(np.float32)
         jobs.append(("rmat", R, synth.transpose(R), torch.float32))
-    for m, d in ((500, 0.03), (1500, 0.01)):
+    for m, d in ((500, 0.03), (1500, 0.01)) + (((4096, 0.005),) if served_sizes else ()):
         A = synth.erdos_renyi(m, m, d, seed=m)
         B = synth.erdos_renyi(m, m, d, seed=m + 1)
         jobs.append(("uniform", A, B, torch.float64))
@@ -62,6 +64,7 @@ def _check_against_alone(reap, pool, reqs, picks):
     refs = {}
     for i, p in enumerate(picks):
         kind, A, B, dA, dB = pool[p]
+        assert reqs[i].status == "ok", "request %d: %s %s" % (i, reqs[i].status, reqs[i].error)
         if p not in alone:
             C = reap.spgemm(dA, dB, c_index_dtype=torch.int64)
             torch.cuda.synchronize()
@@ -79,11 +82,29 @@ def _check_against_alone(reap, pool, reqs, picks):
         compare_full(ref, rp, col, val, val.dtype, "request %d (%s)" % (i, kind))
 
 
+def _footprints(reap, pool):
+    """Device bytes of each job served alone: C (columns + values), int64 row
+    pointers and the workspace a fresh plan holds after its symbolic pass
+    (the serving loop reserves the library's upper bound before that pass and
+    keeps only what was really allocated)."""
+    foot = []
+    for kind, A, B, dA, dB in pool:
+        ref = oracle.spgemm(A, B, with_values=False)
+        with reap.Batch(dA.dtype, torch.int64) as b:
+            assert b.workspace_query([dA], [dB]) >= 0
+            b.symbolic([dA], [dB])
+            ws = b.workspace_bytes
+        foot.append(ref.nnz * (4 + dA.val.element_size()) + (A.rows + 1) * 8 + ws)
+    return foot
+
+
 def test_served_mix_matches_alone(reap):
+    """A mix that includes jobs at the served workload's sizes: every request
+    gives the same result in the mix as alone, and the oracle's."""
     from paper_2004_13907_amd.serve import Server
-    pool = _pool(reap)
+    pool = _pool(reap, served_sizes=True)
     reqs, picks = _requests(reap, pool, 40, qps=4000.0, seed=21)
-    say("served mix: 40 requests, 3 slots")
+    say("served mix: 40 requests, 3 slots, jobs up to R-MAT 14 / stencil 16 / uniform 4096")
     srv = Server(slots=3, hbm_budget_bytes=8e9, max_batch=6)
     try:
         st = srv.run(reqs)
@@ -91,24 +112,51 @@ def test_served_mix_matches_alone(reap):
         srv.close()
     assert st.requests == 40 and all(r.done is not None and r.done >= r.arrival for r in reqs)
     assert st.batches < 40, "requests that arrive together are batched"
+    assert st.peak_bytes <= st.budget_bytes
     _check_against_alone(reap, pool, reqs, picks)
 
 
 def test_served_memory_admission(reap):
     """A budget about twice the largest single request's footprint: batches
-    must shrink or wait for memory, and every result still matches."""
+    must shrink or wait for memory, the accounted peak stays within the
+    budget, and every result still matches."""
     from paper_2004_13907_amd.serve import Server
-    pool = _pool(reap)
-    foot = []
-    for kind, A, B, dA, dB in pool:
-        ref = oracle.spgemm(A, B, with_values=False)
-        foot.append(ref.nnz * (4 + dA.val.element_size()) + (A.rows + 1) * 8)
+    pool = _pool(reap, served_sizes=True)
+    foot = _footprints(reap, pool)
     reqs, picks = _requests(reap, pool, 30, qps=1e5, seed=22)
-    say("served under a tight HBM budget")
-    srv = Server(slots=3, hbm_budget_bytes=2.2 * max(foot) + 4e6, max_batch=8)
+    budget = 2.2 * max(foot)
+    say("served under a tight HBM budget (%.1f MB)" % (budget / 1e6))
+    srv = Server(slots=3, hbm_budget_bytes=budget, max_batch=8)
     try:
         st = srv.run(reqs)
     finally:
         srv.close()
+    assert st.rejected == 0 and st.requests == 30
     assert st.resymbolic + st.waits_for_memory > 0, "the budget never constrained admission"
+    assert st.peak_bytes <= budget, "accounted peak %d above the budget %d" % (st.peak_bytes, budget)
     _check_against_alone(reap, pool, reqs, picks)
+
+
+def test_served_rejects_what_cannot_fit(reap):
+    """A request whose footprint alone exceeds the budget is rejected with a
+    status; the requests around it are served and match."""
+    from paper_2004_13907_amd.serve import Server
+    pool = _pool(reap)
+    foot = _footprints(reap, pool)
+    big = int(np.argmax(foot))
+    budget = 0.9 * foot[big]
+    small = [i for i, f in enumerate(foot) if f * 2 < budget]
+    assert small, "no job small enough for the budget"
+    from paper_2004_13907_amd.serve import Request
+    picks = [small[i % len(small)] for i in range(6)]
+    reqs = [Request(i, pool[p][3], pool[p][4], 0.0, kind=pool[p][0]) for i, p in enumerate(picks)]
+    reqs.append(Request(6, pool[big][3], pool[big][4], 0.0, kind=pool[big][0]))
+    say("served with one request above the budget (%.1f MB)" % (budget / 1e6))
+    srv = Server(slots=2, hbm_budget_bytes=budget, max_batch=4)
+    try:
+        st = srv.run(reqs)
+    finally:
+        srv.close()
+    assert reqs[6].status == "rejected" and st.rejected == 1
+    assert st.peak_bytes <= budget
+    _check_against_alone(reap, pool, reqs[:6], picks)
