@@ -42,8 +42,12 @@ typedef enum {
     REAP_ERR_INDEX_OVERFLOW = 3, /* nnz(C) does not fit the requested C row-pointer type */
     REAP_ERR_OUT_OF_MEMORY = 4,  /* workspace allocation failed */
     REAP_ERR_STATE = 5,          /* numeric called without a matching symbolic */
-    REAP_ERR_HIP = 6             /* a HIP runtime call failed (includes earlier kernel faults) */
+    REAP_ERR_HIP = 6,            /* a HIP runtime call failed (includes earlier kernel faults) */
+    REAP_ERR_TOO_LARGE = 7       /* the product exceeds the static scratch of reap_spgemm_symbolic_noalloc */
 } reap_status_t;
+
+/* Bytes of the per-device static scratch used by reap_spgemm_symbolic_noalloc. */
+#define REAP_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 typedef enum { REAP_F32 = 0, REAP_F64 = 1 } reap_dtype_t;
 typedef enum { REAP_I32 = 0, REAP_I64 = 1 } reap_index_t;
@@ -174,6 +178,35 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype,
 reap_status_t reap_spgemm_symbolic(reap_spgemm_t plan, const reap_csr_t* A, const reap_csr_t* B,
                                    void* c_row_ptr, int64_t* c_nnz, int64_t* n_products,
                                    size_t* workspace_bytes);
+
+/*
+ * Allocation-free variant of reap_spgemm_symbolic, for callers that cannot
+ * allocate memory during the call: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments and
+ * results as reap_spgemm_symbolic for one product (no workspace_bytes), and
+ * the numeric call that follows is unchanged.  The plan's workspace for this
+ * product (counters, per-row classes, counts and column windows, the
+ * long-row list, scan partials, and for FP32 products the long-row FP64
+ * accumulators when a long row reads a B row out of column order) is placed
+ * in a static device array of REAP_NOALLOC_SCRATCH_BYTES (64 MiB) instead of
+ * the plan's own allocation: about 22 bytes per row of A, so products up to
+ * roughly 2.9 million rows.  Larger products return REAP_ERR_TOO_LARGE
+ * before any device work.  The call and the numeric call after it launch
+ * their kernels directly (not through captured graphs, whatever the plan's
+ * `graph` option) and call no hipMalloc, hipFree or other allocating
+ * routine; the plan itself must have been created beforehand.
+ * Sharing: each device holds one such array from the plan creation that
+ * first looked it up until the process ends, and every allocation-free call
+ * on that device uses it, keeping the last call's contents (the counters are
+ * cleared at the start of each call).  Calls that overlap on one device
+ * race, and so does a numeric call whose allocation-free symbolic call was
+ * followed by another one on the same device before it: serialise them (one
+ * stream, or events).  A later reap_spgemm_symbolic on the plan returns it to
+ * its own workspace.
+ * Errors: as reap_spgemm_symbolic, plus TOO_LARGE (never OUT_OF_MEMORY).
+ */
+reap_status_t reap_spgemm_symbolic_noalloc(reap_spgemm_t plan, const reap_csr_t* A, const reap_csr_t* B,
+                                           void* c_row_ptr, int64_t* c_nnz, int64_t* n_products);
 
 /*
  * Numeric pass: multiply, accumulate and write C (Algorithm 1's products,

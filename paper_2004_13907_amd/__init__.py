@@ -29,6 +29,7 @@ __all__ = [
     "spgemm_batch",
     "reap_spgemm_create",
     "reap_spgemm_symbolic",
+    "reap_spgemm_symbolic_noalloc",
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
@@ -166,6 +167,18 @@ def reap_spgemm_symbolic(plan, A: DeviceCSR, B: DeviceCSR, c_row_ptr: torch.Tens
     st = lib.reap_spgemm_symbolic(plan, ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(c_row_ptr.data_ptr()),
                                   ctypes.byref(nnz), ctypes.byref(prods), ctypes.byref(ws))
     return st, int(nnz.value), int(prods.value), int(ws.value)
+
+
+def reap_spgemm_symbolic_noalloc(plan, A: DeviceCSR, B: DeviceCSR, c_row_ptr: torch.Tensor):
+    """The allocation-free symbolic pass; returns (status, nnz(C), partial products)."""
+    lib = _capi.load()
+    a, b = A.c_struct(), B.c_struct()
+    nnz = ctypes.c_int64(0)
+    prods = ctypes.c_int64(0)
+    st = lib.reap_spgemm_symbolic_noalloc(plan, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.c_void_p(c_row_ptr.data_ptr()), ctypes.byref(nnz),
+                                          ctypes.byref(prods))
+    return st, int(nnz.value), int(prods.value)
 
 
 def reap_spgemm_numeric(plan, A: DeviceCSR, B: DeviceCSR, c_row_ptr: torch.Tensor, c_col: torch.Tensor,

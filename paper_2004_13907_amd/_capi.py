@@ -15,6 +15,8 @@ REAP_ERR_INDEX_OVERFLOW = 3
 REAP_ERR_OUT_OF_MEMORY = 4
 REAP_ERR_STATE = 5
 REAP_ERR_HIP = 6
+REAP_ERR_TOO_LARGE = 7
+REAP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 REAP_F32 = 0
 REAP_F64 = 1
@@ -25,6 +27,7 @@ REAP_I64 = 1
 EXPORTED = (
     "reap_spgemm_create",
     "reap_spgemm_symbolic",
+    "reap_spgemm_symbolic_noalloc",
     "reap_spgemm_numeric",
     "reap_spgemm_batch_symbolic",
     "reap_spgemm_batch_numeric",
@@ -104,6 +107,9 @@ def load():
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_size_t)]
     lib.reap_spgemm_symbolic.restype = st
+    lib.reap_spgemm_symbolic_noalloc.argtypes = [P, ctypes.POINTER(reap_csr_t), ctypes.POINTER(reap_csr_t), P,
+                                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.reap_spgemm_symbolic_noalloc.restype = st
     lib.reap_spgemm_numeric.argtypes = [P, ctypes.POINTER(reap_csr_t), ctypes.POINTER(reap_csr_t), P, P, P]
     lib.reap_spgemm_numeric.restype = st
     PP = ctypes.POINTER(P)

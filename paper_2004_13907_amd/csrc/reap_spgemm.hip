@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -55,6 +56,38 @@ constexpr int kNumWavesH = kWaveKernelWaves;
 
 }  // namespace
 
+// Workspace of reap_spgemm_symbolic_noalloc: one array per device, held for
+// the life of the process.  Host code must not pass `scratch` itself to a
+// kernel (in host code the name is a host-side stand-in); it uses the device
+// address looked up by static_scratch() below.
+static __device__ __align__(256) char scratch[REAP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device (with
+// that device current, as it is when a plan is created on it).
+reap_status_t static_scratch(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return REAP_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return REAP_ERR_HIP;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return REAP_OK;
+}
+
+}  // namespace
+
 struct reap_spgemm_s {
     int device = 0;
     int num_cus = 256;
@@ -72,6 +105,9 @@ struct reap_spgemm_s {
 
     Workspace ws;      // counters, per-row arrays, tables
     Workspace gvals;   // long-row FP64 accumulators (FP32 output only)
+    double* gvals_ptr = nullptr;   // accumulators in use: gvals.base, or inside the static scratch
+    bool ws_static = false;        // the workspace pointers below point into the static scratch
+    bool eager = false;            // this call runs its kernels directly (no tables, no graphs)
     Workspace tws;     // scratch of the device transpose
     int64_t cap_rows = -1, cap_prods = 0;
     int32_t cap_blocks = 0, cap_tiles = 0;
@@ -236,11 +272,35 @@ reap_status_t ensure_host(reap_spgemm_s* p, int nprod) {
     return REAP_OK;
 }
 
+// Points the plan's workspace arrays into `b` laid out as L.
+void bind_workspace(reap_spgemm_s* p, char* b, const WsLayout& L) {
+    p->ctr = reinterpret_cast<Counters*>(b + L.o_ctr);
+    p->n_long = reinterpret_cast<unsigned int*>(b + L.o_nlong);
+    p->cls = reinterpret_cast<uint8_t*>(b + L.o_cls);
+    p->rnnz = reinterpret_cast<int32_t*>(b + L.o_rnnz);
+    p->win = reinterpret_cast<int2*>(b + L.o_win);
+    p->long_list = reinterpret_cast<int2*>(b + L.o_long);
+    p->parts = reinterpret_cast<WGPart*>(b + L.o_parts);
+    p->tiles = reinterpret_cast<long long*>(b + L.o_tiles);
+    p->blk_start = reinterpret_cast<int32_t*>(b + L.o_bs);
+    p->tile_start = reinterpret_cast<int32_t*>(b + L.o_ts);
+    p->sym_args = b + L.o_sa;
+    p->num_args = b + L.o_na;
+    p->scan_args = reinterpret_cast<ScanArgs*>(b + L.o_sc);
+}
+
 // Device workspace for the given totals (grows, never shrinks).
 reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, int32_t tiles, int nprod) {
     if (p->ws.base && rows <= p->cap_rows && blocks <= p->cap_blocks && tiles <= p->cap_tiles &&
-        (int64_t)nprod <= p->cap_prods)
+        (int64_t)nprod <= p->cap_prods) {
+        if (p->ws_static) {  // the previous call ran in the static scratch: back to the plan's own
+            bind_workspace(p, static_cast<char*>(p->ws.base),
+                           ws_layout(p->cap_rows, p->cap_blocks, p->cap_tiles, p->cap_prods));
+            p->ws_static = false;
+            ++p->ws_generation;
+        }
         return REAP_OK;
+    }
     const int64_t R = std::max<int64_t>({rows, p->cap_rows, 1});
     const int32_t Bk = std::max({blocks, p->cap_blocks, 1});
     const int32_t Tl = std::max({tiles, p->cap_tiles, 1});
@@ -261,27 +321,30 @@ reap_status_t ensure_workspace(reap_spgemm_s* p, int64_t rows, int32_t blocks, i
         p->cap_prods = 0;
         return REAP_ERR_OUT_OF_MEMORY;
     }
-    char* b = static_cast<char*>(base);
     p->ws.base = base;
     p->ws.bytes = L.total;
-    p->ctr = reinterpret_cast<Counters*>(b + L.o_ctr);
-    p->n_long = reinterpret_cast<unsigned int*>(b + L.o_nlong);
-    p->cls = reinterpret_cast<uint8_t*>(b + L.o_cls);
-    p->rnnz = reinterpret_cast<int32_t*>(b + L.o_rnnz);
-    p->win = reinterpret_cast<int2*>(b + L.o_win);
-    p->long_list = reinterpret_cast<int2*>(b + L.o_long);
-    p->parts = reinterpret_cast<WGPart*>(b + L.o_parts);
-    p->tiles = reinterpret_cast<long long*>(b + L.o_tiles);
-    p->blk_start = reinterpret_cast<int32_t*>(b + L.o_bs);
-    p->tile_start = reinterpret_cast<int32_t*>(b + L.o_ts);
-    p->sym_args = b + L.o_sa;
-    p->num_args = b + L.o_na;
-    p->scan_args = reinterpret_cast<ScanArgs*>(b + L.o_sc);
+    bind_workspace(p, static_cast<char*>(base), L);
+    p->ws_static = false;
     p->cap_rows = R;
     p->cap_blocks = Bk;
     p->cap_tiles = Tl;
     p->cap_prods = Q;
     ++p->ws_generation;
+    return REAP_OK;
+}
+
+// Workspace of one product inside the device's static scratch (no
+// allocation); *used receives the bytes taken.
+reap_status_t bind_static(reap_spgemm_s* p, int64_t rows, int32_t blocks, int32_t tiles, size_t* used) {
+    const WsLayout L = ws_layout(std::max<int64_t>(rows, 1), std::max(blocks, 1), std::max(tiles, 1), 1);
+    if (L.total > (size_t)REAP_NOALLOC_SCRATCH_BYTES) return REAP_ERR_TOO_LARGE;
+    void* base = nullptr;
+    const reap_status_t st = static_scratch(p->device, &base);
+    if (st != REAP_OK) return st;
+    bind_workspace(p, static_cast<char*>(base), L);
+    p->ws_static = true;
+    ++p->ws_generation;
+    *used = L.total;
     return REAP_OK;
 }
 
@@ -332,7 +395,7 @@ BatchMap batch_map(const reap_spgemm_s* p) {
 
 // Argument tables go through device memory for batches and captured passes;
 // a single eager product passes its arguments by value.
-bool use_tables(const reap_spgemm_s* p) { return p->nprod > 1 || p->use_graph; }
+bool use_tables(const reap_spgemm_s* p) { return p->nprod > 1 || (p->use_graph && !p->eager); }
 
 // Runs `body` (which enqueues work on the plan's stream) eagerly, or captures
 // it once per key into a graph and replays that graph.
@@ -519,6 +582,7 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
             if (p->h_ctr[q].bad_csr) return REAP_ERR_BAD_CSR;
     }
 
+    if (!p->use_graph || p->eager) return launch_symbolic<IdxT>(p, a0, s0);
     std::vector<uint64_t> key = {p->ws_generation, (uint64_t)nprod, (uint64_t)p->total_blocks,
                                  (uint64_t)p->total_tiles, (uint64_t)p->total_rows, (uint64_t)p->cidx,
                                  (uint64_t)sizeof(IdxT)};
@@ -559,9 +623,15 @@ size_t gvals_bound(const reap_spgemm_s* p, const BatchTotals& t) {
     return (size_t)stride * (size_t)grid * sizeof(double);
 }
 
+// The symbolic pass of `count` products.  With `noalloc` (one product) the
+// workspace is bound into the device's static scratch instead of the plan's
+// own allocation, the kernels are launched directly, and nothing is
+// allocated on the device or the host heap.
 reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* A, const reap_csr_t* B,
-                             void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes) {
+                             void* const* c_row_ptr, int64_t* c_nnz, int64_t* n_products, size_t* workspace_bytes,
+                             bool noalloc = false) {
     if (!p || count < 1 || count > INT32_MAX / 2 || !A || !B || !c_row_ptr || !c_nnz) return REAP_ERR_INVALID_ARG;
+    if (noalloc && count != 1) return REAP_ERR_INVALID_ARG;
     reap_status_t st;
     const reap_index_t in_idx = A[0].row_ptr_type;
     BatchTotals bt;
@@ -571,8 +641,15 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     const int64_t rows = bt.rows, blocks = bt.blocks, tiles = bt.tiles;
     p->have_symbolic = false;
     if (p->ev_num_upload && p->num_upload_recorded) (void)hipEventSynchronize(p->ev_num_upload);
-    if ((st = ensure_host(p, (int)count)) != REAP_OK) return st;
-    if ((st = ensure_workspace(p, rows, (int32_t)blocks, (int32_t)tiles, (int)count)) != REAP_OK) return st;
+    size_t static_used = 0;
+    if (noalloc) {
+        // the pinned host mirror made at create holds one product's counters
+        if ((st = bind_static(p, rows, (int32_t)blocks, (int32_t)tiles, &static_used)) != REAP_OK) return st;
+    } else {
+        if ((st = ensure_host(p, (int)count)) != REAP_OK) return st;
+        if ((st = ensure_workspace(p, rows, (int32_t)blocks, (int32_t)tiles, (int)count)) != REAP_OK) return st;
+    }
+    p->eager = noalloc;
 
     p->nprod = (int)count;
     p->prods.assign((size_t)count, ProdState{});
@@ -627,30 +704,43 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
         max_group_nnz = std::max(max_group_nnz, h.max_group_nnz);
     }
 
-    // long rows: one numeric workgroup per CU (its LDS takes most of the CU's);
-    // FP32 output needs an FP64 accumulator per workgroup (one segment of the
-    // widest row)
+    // long rows: one numeric workgroup per CU (its LDS takes most of the CU's).
+    // FP32 output needs FP64 accumulators in device memory (one segment of the
+    // widest row per workgroup) only where a long row reads a B row stored
+    // out of column order (the rank-chunk walks need sorted rows)
+    bool unsorted_long = false;
+    for (int q = 0; q < p->nprod; ++q) unsorted_long |= (p->h_ctr[q].bad_csr & kUnsortedB) != 0u;
     p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus));
     p->gvals_stride = 0;
-    if (p->dtype == REAP_F32 && nl > 0) {
+    p->gvals_ptr = nullptr;
+    if (p->dtype == REAP_F32 && nl > 0 && unsorted_long) {
         const int64_t stride =
             std::max<int64_t>(1, std::min<int64_t>((int64_t)max_group_nnz, (int64_t)p->th.group_lds_span));
         const size_t need = (size_t)stride * (size_t)p->long_grid * sizeof(double);
-        if (need > p->gvals.bytes) {
-            (void)hipStreamSynchronize(p->stream);
-            if (p->g_num) {
-                (void)hipGraphExecDestroy(p->g_num);
-                p->g_num = nullptr;
-                p->g_num_key.clear();
+        if (noalloc) {
+            const size_t off = align_up(static_used, 256);
+            if (off + need > (size_t)REAP_NOALLOC_SCRATCH_BYTES) return REAP_ERR_TOO_LARGE;
+            void* base = nullptr;
+            if ((st = static_scratch(p->device, &base)) != REAP_OK) return st;
+            p->gvals_ptr = reinterpret_cast<double*>(static_cast<char*>(base) + off);
+        } else {
+            if (need > p->gvals.bytes) {
+                (void)hipStreamSynchronize(p->stream);
+                if (p->g_num) {
+                    (void)hipGraphExecDestroy(p->g_num);
+                    p->g_num = nullptr;
+                    p->g_num_key.clear();
+                }
+                if (p->gvals.base) (void)hipFree(p->gvals.base);
+                p->gvals.base = nullptr;
+                p->gvals.bytes = 0;
+                if (dev_malloc(p, &p->gvals.base, need) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return REAP_ERR_OUT_OF_MEMORY;
+                }
+                p->gvals.bytes = need;
             }
-            if (p->gvals.base) (void)hipFree(p->gvals.base);
-            p->gvals.base = nullptr;
-            p->gvals.bytes = 0;
-            if (dev_malloc(p, &p->gvals.base, need) != hipSuccess) {
-                (void)hipGetLastError();
-                return REAP_ERR_OUT_OF_MEMORY;
-            }
-            p->gvals.bytes = need;
+            p->gvals_ptr = static_cast<double*>(p->gvals.base);
         }
         p->gvals_stride = stride;
     }
@@ -740,17 +830,20 @@ reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_cs
         a.cls = to_gptr(p->cls + ps.row_off);
         a.win = to_gptr(p->win + ps.row_off);
         a.ctr = to_gptr(p->ctr + q);
-        a.gvals = to_gptr(static_cast<double*>(p->gvals.base));
+        a.gvals = to_gptr(p->gvals_ptr);
         a.gvals_stride = p->gvals_stride;
         a.th = p->th;
         std::memcpy(p->h_stage_num + (size_t)q * sizeof(a), &a, sizeof(a));
         if (q == 0) a0 = a;
     }
+    // after an allocation-free symbolic call the kernels run directly, so that
+    // this call allocates nothing either
+    if (!p->use_graph || p->eager) return launch_numeric<T, IdxT, IdxC>(p, a0);
     std::vector<uint64_t> key = {p->ws_generation, (uint64_t)p->nprod, (uint64_t)p->total_blocks,
                                  (uint64_t)p->long_rows, (uint64_t)p->long_grid,
                                  (uint64_t)(p->agg.cls[kClsWaveBmpS] > 0), (uint64_t)(p->agg.cls[kClsWaveHash] > 0),
                                  (uint64_t)sizeof(T), (uint64_t)sizeof(IdxT), (uint64_t)sizeof(IdxC),
-                                 (uint64_t)(uintptr_t)p->gvals.base, (uint64_t)p->gvals_stride};
+                                 (uint64_t)(uintptr_t)p->gvals_ptr, (uint64_t)p->gvals_stride};
     const reap_status_t st =
         run_pass(p, p->g_num, p->g_num_key, key, [&]() { return launch_numeric<T, IdxT, IdxC>(p, a0); });
     if (st == REAP_OK && p->use_graph) {
@@ -924,6 +1017,7 @@ const char* reap_status_string(reap_status_t s) {
         case REAP_ERR_OUT_OF_MEMORY: return "out of device memory";
         case REAP_ERR_STATE: return "numeric call does not match a preceding symbolic call";
         case REAP_ERR_HIP: return "HIP runtime error";
+        case REAP_ERR_TOO_LARGE: return "product exceeds the static scratch of the allocation-free entry point";
     }
     return "unknown status";
 }
@@ -963,11 +1057,16 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_num_upload, hipEventDisableTiming);
-    if (e != hipSuccess) {
+    void* scratch_ptr = nullptr;
+    if (e != hipSuccess || static_scratch(p->device, &scratch_ptr) != REAP_OK) {
+        // the device address of the static scratch is looked up here, once per
+        // device, with the plan's device current
         (void)hipGetLastError();
+        if (p->ev_num_upload) (void)hipEventDestroy(p->ev_num_upload);
         delete p;
         return REAP_ERR_HIP;
     }
+    p->prods.reserve(1);  // one product's record: the allocation-free call never grows it
     if (ensure_host(p, 1) != REAP_OK) {
         (void)hipEventDestroy(p->ev_num_upload);
         delete p;
@@ -1004,6 +1103,13 @@ reap_status_t reap_spgemm_symbolic(reap_spgemm_t p, const reap_csr_t* A, const r
     if (!p || !A || !B || !c_nnz || !c_row_ptr) return REAP_ERR_INVALID_ARG;
     void* rp[1] = {c_row_ptr};
     return symbolic_batch(p, 1, A, B, rp, c_nnz, n_products, workspace_bytes);
+}
+
+reap_status_t reap_spgemm_symbolic_noalloc(reap_spgemm_t p, const reap_csr_t* A, const reap_csr_t* B, void* c_row_ptr,
+                                           int64_t* c_nnz, int64_t* n_products) {
+    if (!p || !A || !B || !c_nnz || !c_row_ptr) return REAP_ERR_INVALID_ARG;
+    void* rp[1] = {c_row_ptr};
+    return symbolic_batch(p, 1, A, B, rp, c_nnz, n_products, nullptr, true);
 }
 
 reap_status_t reap_spgemm_numeric(reap_spgemm_t p, const reap_csr_t* A, const reap_csr_t* B, const void* c_row_ptr,

@@ -447,20 +447,25 @@ def test_allocation_failure_is_reported(reap):
         assert reap.reap_spgemm_destroy(plan.handle) == _capi.REAP_OK
         plan.handle = None
     say("allocation failure: FP32 long-row accumulators")
-    R = synth.rmat(9, seed=3).astype(np.float32)
-    Rt = synth.transpose(R)
-    dR = reap.DeviceCSR.from_host(R, dtype=torch.float32)
-    dRt = reap.DeviceCSR.from_host(Rt, dtype=torch.float32)
-    with reap.Plan(torch.float32, test_fail_alloc=2) as plan:
+    # long rows over B rows out of column order, in 256-slot chunks: FP32
+    # output then needs device-memory FP64 accumulators (the 2nd allocation)
+    Af = synth.erdos_renyi(200, 2000, 0.05, seed=81, dtype=np.float32)
+    Bf = synth.random_tiny(2000, 20000, 0.03, seed=82, dtype=np.float32, unsorted=True)
+    dAf = reap.DeviceCSR.from_host(Af, dtype=torch.float32)
+    dBf = reap.DeviceCSR.from_host(Bf, dtype=torch.float32)
+    with reap.Plan(torch.float32, test_fail_alloc=2, group_lds_values=256) as plan:
         with pytest.raises(reap.SpGEMMError) as e:
-            plan.symbolic(dR, dRt)
+            plan.symbolic(dAf, dBf)
         assert e.value.status == _capi.REAP_ERR_OUT_OF_MEMORY
-        rp, nnz, _ = plan.symbolic(dR, dRt)
-        col, val = plan.numeric(dR, dRt, rp)
+        rp, nnz, _ = plan.symbolic(dAf, dBf)
+        col, val = plan.numeric(dAf, dBf, rp)
         torch.cuda.synchronize()
-        assert plan.bin_stats()["group"] > 0
-        compare_full(oracle.spgemm(R, Rt), rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), np.float32,
+        assert plan.bin_stats()["long_segments_device"] > 0
+        compare_full(oracle.spgemm(Af, Bf), rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), np.float32,
                      "FP32 long rows after an allocation failure")
+    R = synth.rmat(9, seed=3).astype(np.float32)
+    dR = reap.DeviceCSR.from_host(R, dtype=torch.float32)
+    Rt = synth.transpose(R)
     say("allocation failure: transpose scratch")
     with reap.Plan(torch.float32, test_fail_alloc=1) as plan:
         with pytest.raises(reap.SpGEMMError) as e:
