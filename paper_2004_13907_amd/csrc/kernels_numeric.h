@@ -16,6 +16,7 @@ template <typename T, typename IdxT, typename IdxC>
 struct NumArgs {
     int64_t m;
     int64_t n;
+    int64_t k;                 // rows of B (B's row pointer has k + 1 entries)
     gptr<const IdxT> a_rp;
     gptr<const int32_t> a_col;
     gptr<const T> a_val;

@@ -11,6 +11,7 @@ template <typename IdxT>
 struct SymArgs {
     int64_t m;                 // rows of A
     int64_t n;                 // columns of B
+    int64_t k;                 // rows of B (B's row pointer has k + 1 entries)
     gptr<const IdxT> a_rp;
     gptr<const int32_t> a_col;
     gptr<const IdxT> b_rp;

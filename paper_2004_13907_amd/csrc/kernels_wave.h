@@ -1,19 +1,27 @@
 // Wavefront-per-row kernels: symbolic (row product count, binning, per-row
 // column count) and numeric (products, accumulation, ascending-column write)
-// for rows with at most 64 entries in A whose products fit the grouped lane
-// mapping below in a bounded number of 64-lane steps.
+// for rows whose products fit one wavefront in at most kRowSteps steps.
 //
-// Latency structure.  A wavefront owns a chunk of kRowsPerWave consecutive
-// rows.  The A entries of the whole chunk and the extents of the B rows they
-// name are first staged in LDS (two dependent rounds of loads per chunk, not
-// per row).  For each row every product's B index is then computed from LDS,
-// and all of the row's B gathers are issued back to back before any of them
-// is consumed.
+// Lane mapping of a row's products.  A lane takes kLaneEntries consecutive
+// entries of one B row per step: G = ceil(L / kLaneEntries) lanes cover an A
+// entry whose B row has at most L entries (L = the row's longest B row, G not
+// restricted to powers of two), E = floor(64 / G) A entries share a step, and
+// the row takes S = ceil(nA / E) steps.  Group g of lanes takes the entries
+// g*S .. g*S + S - 1, so the entries side by side in one step are far apart in
+// the row (their B rows share fewer columns).  Every load of the row is issued
+// before any is used.
 //
-// Lane mapping of a row's products: G lanes (a power of two no smaller than
-// the row's longest B row) per A entry, 64/G entries per step; the owner of a
-// lane is a shift away.  Rows whose B rows are longer than 64 entries, or that
-// would need more steps than the kernels hold, are long rows (kernels_long.h).
+// The A entries of kRowsPerWave consecutive rows, with the extent of the B row
+// each names (and, for the numeric pass, the A value), are staged in LDS once
+// per chunk of rows: one 8- or 16-byte LDS read per step gives a lane its
+// entry.
+//
+// Column sets live in a circular LDS bitmap of kWaveBitsWords 32-bit words
+// indexed by the absolute column (word (col >> 5) mod kWaveBitsWords), which
+// holds any row whose columns span fewer than kBmpMaxWords words: no window
+// offset is subtracted per product.  The numeric pass ranks each column by a
+// prefix count per word taken in window order from the row's first word, so
+// the rank of a column is its position in the sorted row (no sort).
 #pragma once
 #include "device_utils.h"
 #include "kernels_numeric.h"
@@ -22,36 +30,58 @@
 
 namespace reap {
 
-// A entries of one chunk of rows, with the extent of the B row each names.
+constexpr int kLaneEntries = 4;                     // consecutive B entries per lane and step
+constexpr int kRowSteps = kWaveMaxProducts / (kWave * kLaneEntries);  // steps of a wavefront row
+constexpr int kBmpMask = kWaveBitsWords - 1;
+constexpr int kBmpMaxWords = kWaveBitsWords - 8;    // the scan starts at an 8-aligned word
+constexpr int kNumStageRows = kRowsPerWave / 2;     // rows per staged chunk in the numeric kernels
+constexpr int kNumStageCap = kStageCap / 2;
+
+// An A entry as staged: the B row it names and, with VALS, its value.
+template <typename IdxT, bool VALS>
+struct StEnt {
+    IdxT b0;       // first B entry of the named row
+    int32_t len;   // its length (clamped to 2^24)
+};
 template <typename IdxT>
-struct WaveStage {
-    int64_t rs0;                       // A.row_ptr of the chunk's first row
-    int32_t rowoff[kRowsPerWave + 1];  // entries of row r: [rowoff[r], rowoff[r+1]) after rs0
-    IdxT b0[kStageCap];                // first B entry of the named row
-    int32_t len[kStageCap];            // its length (clamped to 2^24)
+struct StEnt<IdxT, true> {
+    IdxT b0;
+    int32_t len;
+    double a;
 };
 
-// Stages rows [row0, row0 + nrows).  Returns false (nothing staged) when the
-// chunk has more than kStageCap entries; the caller then loads rows directly.
-template <typename IdxT>
-__device__ __forceinline__ bool stage_chunk(WaveStage<IdxT>& st, int64_t row0, int nrows,
+template <typename IdxT, bool VALS, int ROWS, int CAP>
+struct ChunkStage {
+    int32_t rowoff[ROWS + 1];   // entries of row r: [rowoff[r], rowoff[r + 1])
+    StEnt<IdxT, VALS> ent[CAP];
+};
+
+// Stages rows [row0, row0 + nrows) (nrows <= ROWS).  Returns false (nothing
+// staged) when the chunk has more than CAP entries; rows are then staged one
+// at a time by stage_row.
+template <typename T, typename IdxT, bool VALS, int ROWS, int CAP>
+__device__ __forceinline__ bool stage_chunk(ChunkStage<IdxT, VALS, ROWS, CAP>& st, int64_t row0, int nrows,
                                             const IdxT* __restrict__ a_rp, const int32_t* __restrict__ a_col,
-                                            const IdxT* __restrict__ b_rp) {
+                                            const T* __restrict__ a_val, const IdxT* __restrict__ b_rp) {
     const int lane = lane_id();
     int64_t rpv = 0;
     if (lane <= nrows) rpv = (int64_t)a_rp[row0 + lane];
     const int64_t rs0 = uniform_i64(shfl(rpv, 0));
     const int64_t E = uniform_i64(shfl(rpv, nrows)) - rs0;
-    if (E > kStageCap) return false;
+    if (E > CAP) return false;
     if (lane <= nrows) st.rowoff[lane] = (int32_t)(rpv - rs0);
-    if (lane == 0) st.rs0 = rs0;
-    constexpr int U = kStageCap / kWave;
+    constexpr int U = (CAP + kWave - 1) / kWave;
     int k[U];
+    double a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int x = u * kWave + lane;
         k[u] = 0;
-        if (x < E) k[u] = a_col[rs0 + x];
+        a[u] = 0.0;
+        if (x < E) {
+            k[u] = a_col[rs0 + x];
+            if (VALS) a[u] = (double)a_val[rs0 + x];
+        }
     }
     IdxT x0[U], x1[U];
 #pragma unroll
@@ -68,260 +98,147 @@ __device__ __forceinline__ bool stage_chunk(WaveStage<IdxT>& st, int64_t row0, i
     for (int u = 0; u < U; ++u) {
         const int x = u * kWave + lane;
         if (x < E) {
-            st.b0[x] = x0[u];
-            st.len[x] = (int32_t)min((int64_t)x1[u] - (int64_t)x0[u], (int64_t)(1 << 24));
+            StEnt<IdxT, VALS> en;
+            en.b0 = x0[u];
+            en.len = (int32_t)min((int64_t)x1[u] - (int64_t)x0[u], (int64_t)(1 << 24));
+            if constexpr (VALS) en.a = a[u];
+            st.ent[x] = en;
         }
     }
     wave_sync();
     return true;
 }
 
-// Per-row entry view: lane j < nA gets the j-th entry's B extent, from the
-// stage when staged, else straight from memory.  With VALS the A value is
-// loaded too (issued here, first consumed after the row's gathers).
-template <typename T, typename IdxT, bool VALS>
-__device__ __forceinline__ void row_entries(const WaveStage<IdxT>& st, bool staged, int r, int64_t i,
-                                            const IdxT* __restrict__ a_rp, const int32_t* __restrict__ a_col,
-                                            const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
-                                            int& nA, IdxT& b0, int& len, T& a) {
+// Stages the entries of one row (at most 64) at the start of the stage.
+template <typename T, typename IdxT, bool VALS, int ROWS, int CAP>
+__device__ __forceinline__ void stage_row(ChunkStage<IdxT, VALS, ROWS, CAP>& st, IdxT rs, int nA,
+                                          const int32_t* __restrict__ a_col, const T* __restrict__ a_val,
+                                          const IdxT* __restrict__ b_rp) {
     const int lane = lane_id();
-    b0 = 0;
-    len = 0;
-    a = (T)0;
-    if (staged) {
-        const int off = uniform_i32(st.rowoff[r]);
-        nA = uniform_i32(st.rowoff[r + 1]) - off;
-        const int64_t abase = VALS ? uniform_i64(st.rs0) + off : 0;
-        if (lane < nA && nA <= kWave) {
-            b0 = st.b0[off + lane];
-            len = st.len[off + lane];
-            if (VALS) a = a_val[abase + lane];
-        }
-    } else {
-        const IdxT rs = uniform(a_rp[i]);
-        const int64_t n64 = (int64_t)uniform(a_rp[i + 1]) - (int64_t)rs;
-        nA = (int)min(n64, (int64_t)(kWave + 1));
-        if (lane < nA && nA <= kWave) {
-            const int k = a_col[rs + lane];
-            const IdxT x0 = b_rp[k];
-            const IdxT x1 = b_rp[k + 1];
-            b0 = x0;
-            len = (int)min((int64_t)x1 - (int64_t)x0, (int64_t)(1 << 24));
-            if (VALS) a = a_val[rs + lane];
-        }
+    if (lane < nA) {
+        const int k = a_col[rs + lane];
+        StEnt<IdxT, VALS> en;
+        const IdxT x0 = b_rp[k];
+        const IdxT x1 = b_rp[k + 1];
+        en.b0 = x0;
+        en.len = (int32_t)min((int64_t)x1 - (int64_t)x0, (int64_t)(1 << 24));
+        if constexpr (VALS) en.a = (double)a_val[rs + lane];
+        st.ent[lane] = en;
     }
-}
-
-// One A entry as the product loops see it.
-template <typename IdxT>
-struct Ent {
-    IdxT b0;      // first B index of the entry
-    int32_t len;  // B row length
-};
-
-// Per-wavefront LDS for one row's product mapping.
-template <typename IdxT>
-struct RowTable {
-    Ent<IdxT> ent[kWave];
-    double a[kWave];
-};
-
-struct RowPlan {
-    int P;       // partial products of the row
-    int nIt;     // 64-lane steps
-    int logG;    // log2 of lanes per entry
-    int nA;
-};
-
-// 64-lane steps of a row under the grouped mapping, or a number above every
-// step limit when a B row has more than 64 entries.  Lanes >= nA must carry
-// len = 0.
-__device__ __forceinline__ int grouped_steps(int nA, int len) {
-    const int maxlen = dpp_reduce_max(len);
-    const int logG = maxlen <= 1 ? 0 : 32 - __clz(maxlen - 1);
-    if (logG > 6) return kWaveMaxIt + 1;
-    const int shiftE = 6 - logG;
-    return (nA + (1 << shiftE) - 1) >> shiftE;
-}
-
-// Plans the grouped mapping and writes the row's entry table.  Lanes >= nA
-// must carry len = 0, and the classification guarantees at most MAXIT steps
-// (a longer plan is cut to MAXIT steps; the numeric pass then finds fewer
-// columns than the symbolic pass did and leaves the extra slots zero).
-// `slot` receives this lane's index into tb.a, to be written once the A value
-// has arrived.
-template <typename IdxT, int MAXIT>
-__device__ __forceinline__ RowPlan plan_row(int nA, IdxT b0, int len, RowTable<IdxT>& tb, int& slot) {
-    const int lane = lane_id();
-    RowPlan pl;
-    pl.nA = nA;
-    pl.P = dpp_reduce_sum(len);
-    const int maxlen = dpp_reduce_max(len);
-    pl.logG = min(maxlen <= 1 ? 0 : 32 - __clz(maxlen - 1), 6);  // lanes per entry = 2^logG
-    const int shiftE = 6 - pl.logG;                               // entries per step = 2^shiftE
-    pl.nIt = min((nA + (1 << shiftE) - 1) >> shiftE, MAXIT);
-    slot = lane;
-    if (lane < nA) tb.ent[lane] = Ent<IdxT>{b0, len};
     wave_sync();
-    return pl;
 }
 
-// Gathers a row's products for every step t < pl.nIt: ok[t] says whether this
-// lane holds a product, own[t] is its entry slot in tb, col[t] / bv[t] its B
-// column and value (VALS).  Lanes without a product load the row's first
-// product (`safe`, a valid index) so the loads need no branches; all loads are
-// issued before any is used.
-template <bool VALS, typename T, typename IdxT, int MAXIT>
-__device__ __forceinline__ void row_gather(const RowTable<IdxT>& tb, const RowPlan& pl, IdxT safe,
-                                           const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
-                                           bool (&ok)[MAXIT], int (&own)[MAXIT], int (&col)[MAXIT],
-                                           T (&bv)[MAXIT]) {
+// Reductions over the wavefront for any associative op (result on every lane).
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_reduce(V v, Op op) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Geometry of one row's lane mapping (see the file comment).
+struct RowGeo {
+    int S;    // steps (uniform)
+    int E;    // A entries per step (uniform)
+    int g;    // this lane's group: its entry slot within a step
+    int q0;   // this lane's first offset inside its entry's B row
+};
+
+__device__ __forceinline__ RowGeo row_geo(int L, int nA) {
+    RowGeo r;
+    const int G = max(1, (L + kLaneEntries - 1) / kLaneEntries);   // lanes per A entry, <= 16
+    r.E = kWave / G;
+    r.S = (nA + r.E - 1) / r.E;
     const int lane = lane_id();
-    const int nIt = uniform_i32(pl.nIt);
-    const int nA = uniform_i32(pl.nA);
-    const int logG = uniform_i32(pl.logG);
-    IdxT bidx[MAXIT];
-    // group g of lanes takes entries g*nIt .. g*nIt + nIt - 1, so the entries
-    // side by side in one step are far apart in the row (their B rows share
-    // fewer columns, which keeps LDS atomics from colliding)
-    const int e0 = (lane >> logG) * nIt;
-    const int off = lane & ((1 << logG) - 1);
-#pragma unroll
-    for (int t = 0; t < MAXIT; ++t) {
-        ok[t] = false;
-        own[t] = 0;
-        bidx[t] = safe;
-        if (t < nIt) {
-            const int e = e0 + t;
-            const int ec = min(e, kWave - 1);
-            const Ent<IdxT> en = tb.ent[ec];
-            ok[t] = (e < nA) && (off < en.len);
-            own[t] = ec;
-            bidx[t] = ok[t] ? en.b0 + (IdxT)off : safe;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < MAXIT; ++t) {
-        if (t < nIt) {
-            col[t] = b_col[bidx[t]];
-            if (VALS) bv[t] = b_val[bidx[t]];
-        }
-    }
+    // lane / G exactly: (lane + 1/2) / G is at least 1/(2G) away from an integer
+    r.g = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)G));
+    r.q0 = (lane - r.g * G) * kLaneEntries;
+    return r;
 }
 
-// LDS position of bitmap word w: one spare word after every 32, so words a
-// multiple of 32 apart (columns a multiple of 1024 apart, common in banded
-// matrices) fall in different LDS banks.
-__device__ __forceinline__ int pad_word(int w) { return w + (w >> 5); }
-constexpr int padded_words(int n) { return n + n / 32 + 1; }
-// Row stride of a per-wavefront bitmap: padded_words rounded up to 4 words,
-// so it can be cleared with 16-byte stores.
-constexpr int bitmap_stride(int n) { return (padded_words(n) + 3) & ~3; }
-
-// Clears words [0, padded_words(nw)) of a 16-byte aligned bitmap row (and up
-// to 3 words after them, inside the row stride), four words per lane.
-__device__ __forceinline__ void clear_bitmap(uint32_t* bits, int nw) {
-    for (int x = 4 * lane_id(); x < padded_words(nw); x += 4 * kWave)
-        *reinterpret_cast<uint4*>(bits + x) = make_uint4(0u, 0u, 0u, 0u);
-}
-
-// First B index of the row (the first entry with a non-empty B row).
-template <typename IdxT>
-__device__ __forceinline__ IdxT row_safe_index(IdxT b0, int len) {
-    const uint64_t ne = ballot(len > 0);
-    const int fl = ne ? __ffsll((unsigned long long)ne) - 1 : 0;
-    return shfl(b0, fl);
-}
-
-// Distinct columns of one row (the symbolic pass proper): the row's products
-// are gathered, the column window [min, max] is found, and the columns are
-// set in an LDS bitmap over the window (or, when the window is wider than
-// th.wave_max_span, inserted in an LDS hash set).  Lanes without a product set
-// a bit in the dummy word bits[kWaveBitsWords], so no lane needs a branch.
-template <typename IdxT, int MAXIT>
-__device__ __forceinline__ void sym_row(const RowTable<IdxT>& tb, const RowPlan& pl, IdxT safe,
-                                        const int32_t* __restrict__ b_col, uint32_t* bits, const Thresholds& th,
-                                        uint8_t& cls, int& nnz, int2& win) {
-    const int lane = lane_id();
-    const int nIt = uniform_i32(pl.nIt);
-    bool ok[MAXIT];
-    int own[MAXIT];
-    int col[MAXIT];
-    float bv_unused[MAXIT];
-    row_gather<false, float, IdxT, MAXIT>(tb, pl, safe, b_col, nullptr, ok, own, col, bv_unused);
-    int cmin = INT32_MAX, cmax = -1;
+// Issues every load of this lane's products of a row: for step t < S the
+// lane's B entries b0 + q0 + u (u < kLaneEntries) of its A entry, rem[t] of
+// which belong to the row (the rest are loaded but never used).  Loads stay
+// inside B: lanes without an entry read from index 0, and a lane whose four
+// entries would pass the last one (lastB) clamps them.
+template <typename T, typename IdxT, bool VALS>
+__device__ __forceinline__ void row_loads(const StEnt<IdxT, VALS>* ent, int nA, const RowGeo& rg, IdxT lastB,
+                                          const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
+                                          int32_t (&c)[kRowSteps][kLaneEntries], T (&v)[kRowSteps][kLaneEntries],
+                                          int (&rem)[kRowSteps], double (&a)[kRowSteps]) {
 #pragma unroll
-    for (int t = 0; t < MAXIT; ++t) {
-        if (t < nIt) {
-            cmin = ok[t] ? min(cmin, col[t]) : cmin;
-            cmax = ok[t] ? max(cmax, col[t]) : cmax;
-        }
-    }
-    cmin = dpp_reduce_min(cmin);
-    cmax = dpp_reduce_max(cmax);
-    const int64_t span = (int64_t)cmax - cmin + 1;
-    if (span <= th.wave_max_span) {
-        const int nw = (int)((span + 31) >> 5);
-        clear_bitmap(bits, nw);
-        wave_sync();
+    for (int t = 0; t < kRowSteps; ++t) {
+        rem[t] = 0;
+        a[t] = 0.0;
+        if (t < rg.S) {
+            const int e = rg.g * rg.S + t;
+            const bool act = rg.g < rg.E && e < nA;
+            const StEnt<IdxT, VALS> en = ent[act ? e : 0];
+            rem[t] = act ? en.len - rg.q0 : 0;
+            if constexpr (VALS) a[t] = en.a;
+            const IdxT base = act ? en.b0 + (IdxT)rg.q0 : (IdxT)0;
+            if (base + (IdxT)(kLaneEntries - 1) <= lastB) {
 #pragma unroll
-        for (int t = 0; t < MAXIT; ++t) {
-            if (t < nIt) {
-                const int d = ok[t] ? col[t] - cmin : kWaveBitsWords * 32;
-                atomicOr(&bits[pad_word(d >> 5)], 1u << (d & 31));
-            }
-        }
-        wave_sync();
-        int pc = 0;
-        for (int x = lane; x < nw; x += kWave) pc += __popc(bits[pad_word(x)]);
-        nnz = dpp_reduce_sum(pc);
-        win = make_int2(cmin, nw);
-        // the compact bitmap class, or the long-row kernels
-        cls = (nnz <= th.wave_small_nnz && nw <= kWaveSmallWords && uniform_i32(pl.P) <= kWaveSmallProducts)
-                  ? kClsWaveBmpS
-                  : kClsGroup;
-    } else if (uniform_i32(pl.P) <= th.wave_hash_products && nIt <= kWaveHashIt) {
-        for (int x = lane; x < kWaveHashSlots; x += kWave) bits[x] = 0xFFFFFFFFu;
-        wave_sync();
-        int mine = 0;
+                for (int u = 0; u < kLaneEntries; ++u) {
+                    c[t][u] = b_col[base + u];
+                    if (VALS) v[t][u] = b_val[base + u];
+                }
+            } else {
 #pragma unroll
-        for (int t = 0; t < MAXIT; ++t) {
-            if (t < nIt && ok[t]) {
-                const uint32_t key = (uint32_t)col[t];
-                uint32_t h = hash_col(col[t]) >> (32 - 9);
-                while (true) {
-                    const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
-                    if (old == 0xFFFFFFFFu) {
-                        ++mine;
-                        break;
-                    }
-                    if (old == key) break;
-                    h = (h + 1) & (kWaveHashSlots - 1);
+                for (int u = 0; u < kLaneEntries; ++u) {
+                    const IdxT idx = min(base + (IdxT)u, lastB);
+                    c[t][u] = b_col[idx];
+                    if (VALS) v[t][u] = b_val[idx];
                 }
             }
         }
-        nnz = dpp_reduce_sum(mine);
-        cls = kClsWaveHash;
     }
-    wave_sync();
+}
+
+// Column of slot (t, u), or 0xFFFFFFFF when the slot holds no product.
+__device__ __forceinline__ uint32_t slot_col(const int32_t (&c)[kRowSteps][kLaneEntries], const int (&rem)[kRowSteps],
+                                             int t, int u) {
+    return u < rem[t] ? (uint32_t)c[t][u] : 0xFFFFFFFFu;
+}
+
+// Clears the circular bitmap: four 16-byte stores per lane, lanes side by side.
+__device__ __forceinline__ void bmp_clear(uint32_t* bits) {
+#pragma unroll
+    for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j)
+        *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane_id())) = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__device__ __forceinline__ void bmp_set(uint32_t* bits, uint32_t col) {
+    atomicOr(&bits[(col >> 5) & kBmpMask], 1u << (col & 31));
+}
+
+// Set bits of the whole bitmap, summed over the wavefront.
+__device__ __forceinline__ int bmp_count(const uint32_t* bits) {
+    int pc = 0;
+#pragma unroll
+    for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j) {
+        const uint4 q = *reinterpret_cast<const uint4*>(bits + 4 * (j * kWave + lane_id()));
+        pc += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+    }
+    return dpp_reduce_sum(pc);
 }
 
 // ---------------------------------------------------------------------------
 // Symbolic, one wavefront per row.  Classifies every row and counts the
-// distinct columns of rows that stay here: an LDS bitmap over the row's column
-// window [min, max] when it spans at most th.wave_max_span columns, else an
-// LDS hash set when the row has at most th.wave_hash_products products.  Rows
-// with more than 64 entries or th.wave_max_products products go to the
-// long-row list.
+// distinct columns of rows that stay here: the circular LDS bitmap when the
+// row's columns span at most th.wave_max_span columns (and kBmpMaxWords
+// words), else an LDS hash set when the row has at most th.wave_hash_products
+// products.  Rows with more than 64 entries in A, a B row longer than
+// kLaneEntries * 16, more than kRowSteps steps, more than
+// th.wave_max_products products, or more entries of C than the wavefront
+// numeric kernels hold go to the long-row list.
 // TAB: arguments from the batch table (else the by-value argument of a single product).
 template <typename IdxT, bool TAB>
-__global__ void __launch_bounds__(kWaveKernelWaves * 64) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(kWaveKernelWaves * 64)
 k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     constexpr int W = kWaveKernelWaves;
-    constexpr int MAXIT = kWaveMaxIt;
-    __shared__ __align__(16) uint32_t s_bits[W][bitmap_stride(kWaveBitsWords)];  // padded, + a dummy word
-    __shared__ RowTable<IdxT> s_tb[W];
-    __shared__ WaveStage<IdxT> s_stage[W];
+    __shared__ __align__(16) uint32_t s_bits[W][kWaveBitsWords];
+    __shared__ __align__(16) ChunkStage<IdxT, false, kRowsPerWave, kStageCap> s_stage[W];
     __shared__ WGPart s_part[W];
 
     const int w = threadIdx.x / kWave;
@@ -332,41 +249,120 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     const SymArgs<IdxT> p = TAB ? P[q] : p0;
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     uint32_t* bits = s_bits[w];
-    RowTable<IdxT>& tb = s_tb[w];
-    WaveStage<IdxT>& st = s_stage[w];
+    auto& st = s_stage[w];
 
     unsigned long long prod_acc = 0;
     unsigned int cnt[kNumClasses] = {0, 0, 0, 0, 0};
     unsigned int maxp = 0, maxn = 0;
     uint32_t group_flags = 0;
+    // row r's results are kept by lane r and stored together at the end
+    uint8_t my_cls = 0;
+    int my_nnz = 0;
+    int2 my_win = make_int2(0, 0);
 
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
-    const bool staged = nrows > 0 && stage_chunk<IdxT>(st, row0, nrows, p.a_rp, p.a_col, p.b_rp);
+    const bool staged = nrows > 0 && stage_chunk<float, IdxT, false>(st, row0, nrows, p.a_rp, p.a_col,
+                                                                        (const float*)nullptr, p.b_rp);
+    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
 
     for (int r = 0; r < nrows; ++r) {
         const int64_t i = row0 + r;
-        int nA;
-        IdxT b0;
-        int len;
-        float a_unused;
-        row_entries<float, IdxT, false>(st, staged, r, i, p.a_rp, p.a_col, nullptr, p.b_rp, nA, b0, len, a_unused);
+        int nA, off;
+        if (staged) {
+            off = uniform_i32(st.rowoff[r]);
+            nA = uniform_i32(st.rowoff[r + 1]) - off;
+        } else {
+            const IdxT rs = uniform(p.a_rp[i]);
+            nA = (int)min((int64_t)uniform(p.a_rp[i + 1]) - (int64_t)rs, (int64_t)kWave + 1);
+            off = 0;
+            if (nA <= kWave) stage_row<float, IdxT, false>(st, rs, nA, p.a_col, (const float*)nullptr, p.b_rp);
+        }
         uint8_t cls = kClsGroup;
         int nnz = 0;
         int2 win = make_int2(0, 0);
         if (nA == 0) {
             cls = kClsEmpty;
         } else if (nA <= kWave) {
+            const StEnt<IdxT, false>* ent = st.ent + off;
+            const int len = lane < nA ? ent[lane].len : 0;
             const int P = dpp_reduce_sum(len);
+            const int L = dpp_reduce_max(len);
+            const bool fits = P <= p.th.wave_max_products && L <= kLaneEntries * 16;
+            const RowGeo rg = row_geo(fits ? L : 1, nA);
             if (P == 0) {
                 cls = kClsEmpty;
-            } else if (P <= p.th.wave_max_products && grouped_steps(nA, len) <= kWaveSmallIt) {
-                // the grouped lane mapping fits: the row stays with one wavefront
-                // (bitmap or hash); rows that would need the flattened mapping or
-                // the large bitmap class go to the long-row kernels
-                int slot_unused;
-                const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot_unused);
-                const IdxT safe = row_safe_index(b0, len);
-                sym_row<IdxT, MAXIT>(tb, pl, safe, p.b_col, bits, p.th, cls, nnz, win);
+            } else if (fits && rg.S <= kRowSteps) {
+                int32_t c[kRowSteps][kLaneEntries];
+                float v_unused[kRowSteps][kLaneEntries];
+                int rem[kRowSteps];
+                double a_unused[kRowSteps];
+                row_loads<float, IdxT, false>(ent, nA, rg, lastB, p.b_col, nullptr, c, v_unused, rem, a_unused);
+                uint32_t cmin = 0xFFFFFFFFu;
+                int cmax = -1;
+#pragma unroll
+                for (int t = 0; t < kRowSteps; ++t) {
+                    if (t < rg.S) {
+#pragma unroll
+                        for (int u = 0; u < kLaneEntries; ++u) {
+                            const uint32_t cc = slot_col(c, rem, t, u);
+                            cmin = min(cmin, cc);
+                            cmax = max(cmax, (int)cc);
+                        }
+                    }
+                }
+                cmin = wave_reduce(cmin, [](uint32_t x, uint32_t y) { return min(x, y); });
+                cmax = dpp_reduce_max(cmax);
+                const int nw = (cmax >> 5) - (int)(cmin >> 5) + 1;
+                if (nw <= kBmpMaxWords && (int64_t)cmax - (int64_t)cmin + 1 <= (int64_t)p.th.wave_max_span) {
+                    bmp_clear(bits);
+                    wave_sync();
+#pragma unroll
+                    for (int t = 0; t < kRowSteps; ++t) {
+                        if (t < rg.S) {
+#pragma unroll
+                            for (int u = 0; u < kLaneEntries; ++u) {
+                                const uint32_t cc = slot_col(c, rem, t, u);
+                                if ((int)cc >= 0) bmp_set(bits, cc);
+                            }
+                        }
+                    }
+                    wave_sync();
+                    nnz = bmp_count(bits);
+                    win = make_int2((int)cmin, nw);
+                    cls = nnz <= p.th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
+                } else if (P <= p.th.wave_hash_products) {
+                    // an LDS hash set of the row's columns (the bitmap area, kWaveHashSlots keys)
+#pragma unroll
+                    for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)
+                        *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) =
+                            make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                    wave_sync();
+                    int mine = 0;
+#pragma unroll
+                    for (int t = 0; t < kRowSteps; ++t) {
+                        if (t < rg.S) {
+#pragma unroll
+                            for (int u = 0; u < kLaneEntries; ++u) {
+                                const uint32_t key = slot_col(c, rem, t, u);
+                                if ((int)key >= 0) {
+                                    uint32_t h = hash_col((int)key) >> (32 - 9);
+                                    while (true) {
+                                        const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
+                                        if (old == 0xFFFFFFFFu) {
+                                            ++mine;
+                                            break;
+                                        }
+                                        if (old == key) break;
+                                        h = (h + 1) & (kWaveHashSlots - 1);
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    nnz = dpp_reduce_sum(mine);
+                    cls = kClsWaveHash;
+                }
+                wave_sync();
                 if (cls != kClsGroup) {
                     prod_acc += (unsigned long long)P;
                     maxp = max(maxp, (unsigned)P);
@@ -374,16 +370,21 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
                 }
             }
         }
-        if (lane == 0) {
-            p.cls[i] = cls;
-            if (cls != kClsGroup) {
-                p.rnnz[i] = nnz;
-                p.win[i] = win;
-            }
+        if (lane == r) {
+            my_cls = cls;
+            my_nnz = nnz;
+            my_win = win;
         }
 #pragma unroll
-        for (int c = 0; c < kNumClasses; ++c) cnt[c] += (cls == c) ? 1u : 0u;
+        for (int cl = 0; cl < kNumClasses; ++cl) cnt[cl] += (cls == cl) ? 1u : 0u;
         if (cls == kClsGroup) group_flags |= 1u << r;
+    }
+    if (lane < nrows) {
+        p.cls[row0 + lane] = my_cls;
+        if (my_cls != kClsGroup) {
+            p.rnnz[row0 + lane] = my_nnz;
+            p.win[row0 + lane] = my_win;
+        }
     }
 
     // append this wavefront's long rows to the batch's list with one atomic
@@ -399,159 +400,175 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     if (lane == 0) {
         WGPart& s = s_part[w];
         s.products = prod_acc;
-        for (int c = 0; c < kNumClasses; ++c) s.cls[c] = cnt[c];
+        for (int cl = 0; cl < kNumClasses; ++cl) s.cls[cl] = cnt[cl];
         s.max_prod = maxp;
         s.max_nnz = maxn;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         WGPart t = s_part[0];
-        for (int v = 1; v < W; ++v) {
-            t.products += s_part[v].products;
-            for (int c = 0; c < kNumClasses; ++c) t.cls[c] += s_part[v].cls[c];
-            t.max_prod = max(t.max_prod, s_part[v].max_prod);
-            t.max_nnz = max(t.max_nnz, s_part[v].max_nnz);
+        for (int x = 1; x < W; ++x) {
+            t.products += s_part[x].products;
+            for (int cl = 0; cl < kNumClasses; ++cl) t.cls[cl] += s_part[x].cls[cl];
+            t.max_prod = max(t.max_prod, s_part[x].max_prod);
+            t.max_nnz = max(t.max_nnz, s_part[x].max_nnz);
         }
         p.parts[blk] = t;
     }
 }
 
-// Numeric work of one row: gather, bitmap over the window, per-word prefix
-// counts, rank each product's column, accumulate, write the sorted row.
-// Lanes without a product aim at the dummy word bits[pad_word(WMAX)] and the dummy slot
-// vals[NCMAX], so no lane needs a branch.
-template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT>
-__device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int64_t i, RowTable<IdxT>& tb,
-                                            const RowPlan& pl, IdxT safe, int slot, bool has_entry, T a,
-                                            uint32_t* bits, uint32_t* pfx, double* vals, int32_t* cols_l) {
-    const int lane = lane_id();
-    const int nIt = uniform_i32(pl.nIt);
-    bool ok[MAXIT];
-    int own[MAXIT];
-    int col[MAXIT];
-    T bv[MAXIT];
-    row_gather<true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
-    const int2 wn = p.win[i];
-    const int lo = uniform_i32(wn.x), nw = uniform_i32(wn.y);
-    const int64_t cb = uniform((int64_t)p.c_rp[i]);
-    const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
-    if (has_entry) tb.a[slot] = (double)a;
-    clear_bitmap(bits, nw);
-    for (int x = lane; x < nc; x += kWave) vals[x] = 0.0;
-    wave_sync();
-    int dd[MAXIT];
-    double prod[MAXIT];
-    const int ge0 = (lane >> uniform_i32(pl.logG)) * nIt;
-#pragma unroll
-    for (int t = 0; t < MAXIT; ++t) {
-        if (t < nIt) {
-            const int d = ok[t] ? col[t] - lo : WMAX * 32;
-            dd[t] = d;
-            atomicOr(&bits[pad_word(d >> 5)], 1u << (d & 31));
-            const int ow = min(ge0 + t, kWave - 1);
-            prod[t] = tb.a[ow] * (double)bv[t];
-        }
-    }
-    wave_sync();
-    // prefix count of set bits per word: lane l owns words [l*per, l*per + per)
-    const int per = (nw + kWave - 1) / kWave;
-    const int w0 = min(lane * per, nw), w1 = min(w0 + per, nw);
-    int local = 0;
-    for (int x = w0; x < w1; ++x) local += __popc(bits[pad_word(x)]);
-    int run = dpp_incl_scan(local) - local;
-    for (int x = w0; x < w1; ++x) {
-        const uint32_t word = bits[pad_word(x)];
-        pfx[pad_word(x)] = (uint32_t)run;
-        run += __popc(word);
-    }
-    wave_sync();
-#pragma unroll
-    for (int t = 0; t < MAXIT; ++t) {
-        if (t < nIt) {
-            const int d = dd[t];
-            const int pw = pad_word(d >> 5);
-            int rk = (int)pfx[pw] + __popc(bits[pw] & ((1u << (d & 31)) - 1u));
-            rk = (ok[t] && rk < nc) ? rk : NCMAX;  // rk < nc whenever the pattern matches the symbolic pass
-            atomicAdd(&vals[rk], prod[t]);
-            cols_l[rk] = d + lo;
-        }
-    }
-    wave_sync();
-    for (int x = lane; x < nc; x += kWave) {
-        p.c_col[cb + x] = cols_l[x];
-        p.c_val[cb + x] = (T)vals[x];
-    }
-    wave_sync();
-}
-
 // ---------------------------------------------------------------------------
-// Numeric, one wavefront per row of class `want` (bitmap window of at most WMAX
-// words, at most NCMAX entries).  The bitmap words and their prefix counts are
-// two 32-bit LDS arrays (dense words, so the bitmap ORs of a step spread over
-// the banks), and a column's rank (its position in the sorted row) is two LDS
-// reads plus a popcount.
-template <typename T, typename IdxT, typename IdxC, int NCMAX, int WMAX, int MAXIT, int W, bool TAB>
-__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
+// Numeric, one wavefront per row of the compact bitmap class (at most NCMAX
+// entries of C, columns spanning fewer than kBmpMaxWords words): products
+// held in registers, circular bitmap of the row's columns, per-word prefix
+// counts in window order, each product added into the LDS slot of its
+// column's rank, the row written in ascending column order.
+template <typename T, typename IdxT, typename IdxC, int NCMAX, int W, bool TAB>
+__global__ void __launch_bounds__(W * 64)
 k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
-    __shared__ __align__(16) uint32_t s_bits[W][bitmap_stride(WMAX)];  // bitmap words (padded, + dummy)
-    __shared__ uint32_t s_pfx[W][padded_words(WMAX)];                  // set bits before each word
+    __shared__ __align__(16) uint32_t s_bits[W][kWaveBitsWords];
+    __shared__ __align__(16) uint16_t s_pfx[W][kWaveBitsWords];
     __shared__ double s_vals[W][NCMAX + 1];
     __shared__ int32_t s_cols[W][NCMAX + 1];
-    __shared__ RowTable<IdxT> s_tb[W];
-    __shared__ WaveStage<IdxT> s_stage[W];
+    __shared__ __align__(16) ChunkStage<IdxT, true, kNumStageRows, kNumStageCap> s_stage[W];
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
     uint32_t* bits = s_bits[w];
-    uint32_t* pfx = s_pfx[w];
+    uint16_t* pfx = s_pfx[w];
     double* vals = s_vals[w];
     int32_t* cols_l = s_cols[w];
-    RowTable<IdxT>& tb = s_tb[w];
-    WaveStage<IdxT>& st = s_stage[w];
+    auto& st = s_stage[w];
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
     const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
     const NumArgs<T, IdxT, IdxC> p = TAB ? P[q] : p0;
-    const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
-    const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
-    const bool mine = lane < nrows && p.cls[row0 + lane] == want;
-    uint64_t todo = ballot(mine);
-    if (!todo) return;
-    const bool staged = stage_chunk<IdxT>(st, row0, nrows, p.a_rp, p.a_col, p.b_rp);
+    const int64_t rowc = ((int64_t)blk * W + w) * kRowsPerWave;
+    const int nall = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - rowc));
+    const uint64_t todo_all = ballot(lane < nall && p.cls[rowc + lane] == want);
+    if (!todo_all) return;
+    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
 
-    while (todo) {
-        const int r = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t i = row0 + r;
-        int nA;
-        IdxT b0;
-        int len;
-        T a;
-        row_entries<T, IdxT, true>(st, staged, r, i, p.a_rp, p.a_col, p.a_val, p.b_rp, nA, b0, len, a);
-        int slot;
-        const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot);
-        const IdxT safe = row_safe_index(b0, len);
-        num_row_bmp<T, IdxT, IdxC, NCMAX, WMAX, MAXIT>(p, i, tb, pl, safe, slot, len > 0, a, bits, pfx, vals,
-                                                       cols_l);
+    for (int h = 0; h < kRowsPerWave / kNumStageRows; ++h) {
+        const int64_t row0 = rowc + h * kNumStageRows;
+        uint64_t todo = (todo_all >> (h * kNumStageRows)) & ((1ull << kNumStageRows) - 1);
+        if (!todo) continue;
+        const int nrows = (int)max((int64_t)0, min((int64_t)kNumStageRows, p.m - row0));
+        const bool staged = stage_chunk<T, IdxT, true>(st, row0, nrows, p.a_rp, p.a_col, p.a_val, p.b_rp);
+        while (todo) {
+            const int r = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t i = row0 + r;
+            int nA, off;
+            if (staged) {
+                off = uniform_i32(st.rowoff[r]);
+                nA = uniform_i32(st.rowoff[r + 1]) - off;
+            } else {
+                const IdxT rs = uniform(p.a_rp[i]);
+                nA = (int)((int64_t)uniform(p.a_rp[i + 1]) - (int64_t)rs);
+                off = 0;
+                stage_row<T, IdxT, true>(st, rs, nA, p.a_col, p.a_val, p.b_rp);
+            }
+            const StEnt<IdxT, true>* ent = st.ent + off;
+            const int L = dpp_reduce_max(lane < nA ? ent[lane].len : 0);
+            const RowGeo rg = row_geo(L, nA);
+            int32_t c[kRowSteps][kLaneEntries];
+            T v[kRowSteps][kLaneEntries];
+            int rem[kRowSteps];
+            double a[kRowSteps];
+            row_loads<T, IdxT, true>(ent, nA, rg, lastB, p.b_col, p.b_val, c, v, rem, a);
+            const int2 wn = p.win[i];
+            const int lo_w = uniform_i32(wn.x) >> 5;
+            const int64_t cb = uniform((int64_t)p.c_rp[i]);
+            const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
+            bmp_clear(bits);
+            for (int x = lane; x < nc; x += kWave) vals[x] = 0.0;
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < kRowSteps; ++t) {
+                if (t < rg.S) {
+#pragma unroll
+                    for (int u = 0; u < kLaneEntries; ++u) {
+                        const uint32_t cc = slot_col(c, rem, t, u);
+                        if ((int)cc >= 0) bmp_set(bits, cc);
+                    }
+                }
+            }
+            wave_sync();
+            // prefix counts in window order: lane l owns the 16 words from
+            // s0 + 16 l (circularly), s0 the row's first word rounded down to 8
+            {
+                const int s0 = (lo_w & kBmpMask) & ~7;
+                const int wb = (s0 + 16 * lane) & kBmpMask;
+                uint32_t wd[16];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint4 qv = *reinterpret_cast<const uint4*>(bits + ((wb + 4 * k) & kBmpMask));
+                    wd[4 * k] = qv.x;
+                    wd[4 * k + 1] = qv.y;
+                    wd[4 * k + 2] = qv.z;
+                    wd[4 * k + 3] = qv.w;
+                }
+                int local = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) local += __popc(wd[k]);
+                int run = dpp_incl_scan(local) - local;
+                uint32_t pk[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int r0 = run;
+                    run += __popc(wd[2 * k]);
+                    pk[k] = (uint32_t)r0 | ((uint32_t)run << 16);
+                    run += __popc(wd[2 * k + 1]);
+                }
+                uint32_t* pfx32 = reinterpret_cast<uint32_t*>(pfx);
+                *reinterpret_cast<uint4*>(pfx32 + wb / 2) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+                *reinterpret_cast<uint4*>(pfx32 + ((wb + 8) & kBmpMask) / 2) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+            }
+            wave_sync();
+#pragma unroll
+            for (int t = 0; t < kRowSteps; ++t) {
+                if (t < rg.S) {
+#pragma unroll
+                    for (int u = 0; u < kLaneEntries; ++u) {
+                        const uint32_t cc = slot_col(c, rem, t, u);
+                        if ((int)cc >= 0) {
+                            const int wi = (int)((cc >> 5) & kBmpMask);
+                            const uint32_t below = (1u << (cc & 31)) - 1u;
+                            int rk = (int)pfx[wi] + __popc(bits[wi] & below);
+                            rk = rk < nc ? rk : NCMAX;  // rk < nc whenever the pattern matches the symbolic pass
+                            atomicAdd(&vals[rk], a[t] * (double)v[t][u]);
+                            cols_l[rk] = (int32_t)cc;
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            for (int x = lane; x < nc; x += kWave) {
+                p.c_col[cb + x] = cols_l[x];
+                p.c_val[cb + x] = (T)vals[x];
+            }
+            wave_sync();
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Numeric, one wavefront per row whose column window is too wide for a bitmap
-// (at most kWaveHashProducts products): LDS hash table keyed by column, then
-// the occupied slots are compacted and each entry is placed by counting the
-// smaller columns.
+// Numeric, one wavefront per row whose columns span too wide a window for the
+// bitmap (at most kWaveHashProducts products): LDS hash table keyed by
+// column, then the occupied slots are compacted and each entry is placed by
+// counting the smaller columns.
 template <typename T, typename IdxT, typename IdxC, int W, bool TAB>
-__global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P,
-                                                          BatchMap bm, uint8_t want) {
-    constexpr int MAXIT = kWaveHashIt;
-    __shared__ uint32_t s_keys[W][kWaveHashSlots];
+__global__ void __launch_bounds__(W * 64)
+k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
+    constexpr int NC = kWaveHashProducts;
+    constexpr int NCU = NC / kWave;
+    __shared__ __align__(16) uint32_t s_keys[W][kWaveHashSlots];
     __shared__ double s_hv[W][kWaveHashSlots];
-    __shared__ int32_t s_ck[W][kWaveHashProducts];
-    __shared__ double s_cv[W][kWaveHashProducts];
-    __shared__ RowTable<IdxT> s_tb[W];
-    __shared__ WaveStage<IdxT> s_stage[W];
+    __shared__ int32_t s_ck[W][NC];
+    __shared__ double s_cv[W][NC];
+    __shared__ __align__(16) ChunkStage<IdxT, true, kNumStageRows, kNumStageCap> s_stage[W];
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -559,95 +576,109 @@ __global__ void __launch_bounds__(W * 64) k_num_wave_hash(NumArgs<T, IdxT, IdxC>
     double* hv = s_hv[w];
     int32_t* ck = s_ck[w];
     double* cv = s_cv[w];
-    RowTable<IdxT>& tb = s_tb[w];
-    WaveStage<IdxT>& st = s_stage[w];
+    auto& st = s_stage[w];
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
     const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
     const NumArgs<T, IdxT, IdxC> p = TAB ? P[q] : p0;
-    const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
-    const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
-    const bool mine = lane < nrows && p.cls[row0 + lane] == want;
-    uint64_t todo = ballot(mine);
-    if (!todo) return;
-    const bool staged = stage_chunk<IdxT>(st, row0, nrows, p.a_rp, p.a_col, p.b_rp);
+    const int64_t rowc = ((int64_t)blk * W + w) * kRowsPerWave;
+    const int nall = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - rowc));
+    const uint64_t todo_all = ballot(lane < nall && p.cls[rowc + lane] == want);
+    if (!todo_all) return;
+    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
 
-    while (todo) {
-        const int r = __ffsll((unsigned long long)todo) - 1;
-        todo &= todo - 1;
-        const int64_t i = row0 + r;
-        int nA;
-        IdxT b0;
-        int len;
-        T a;
-        row_entries<T, IdxT, true>(st, staged, r, i, p.a_rp, p.a_col, p.a_val, p.b_rp, nA, b0, len, a);
-        int slot;
-        const RowPlan pl = plan_row<IdxT, MAXIT>(nA, b0, len, tb, slot);
-        const IdxT safe = row_safe_index(b0, len);
-        bool ok[MAXIT];
-        int own[MAXIT];
-        int col[MAXIT];
-        T bv[MAXIT];
-        row_gather<true, T, IdxT, MAXIT>(tb, pl, safe, p.b_col, p.b_val, ok, own, col, bv);
-        const int64_t cb = uniform((int64_t)p.c_rp[i]);
-        if (len > 0) tb.a[slot] = (double)a;
-        for (int x = lane; x < kWaveHashSlots; x += kWave) {
-            keys[x] = kEmpty;
-            hv[x] = 0.0;
-        }
-        wave_sync();
+    for (int h = 0; h < kRowsPerWave / kNumStageRows; ++h) {
+        const int64_t row0 = rowc + h * kNumStageRows;
+        uint64_t todo = (todo_all >> (h * kNumStageRows)) & ((1ull << kNumStageRows) - 1);
+        if (!todo) continue;
+        const int nrows = (int)max((int64_t)0, min((int64_t)kNumStageRows, p.m - row0));
+        const bool staged = stage_chunk<T, IdxT, true>(st, row0, nrows, p.a_rp, p.a_col, p.a_val, p.b_rp);
+        while (todo) {
+            const int r = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t i = row0 + r;
+            int nA, off;
+            if (staged) {
+                off = uniform_i32(st.rowoff[r]);
+                nA = uniform_i32(st.rowoff[r + 1]) - off;
+            } else {
+                const IdxT rs = uniform(p.a_rp[i]);
+                nA = (int)((int64_t)uniform(p.a_rp[i + 1]) - (int64_t)rs);
+                off = 0;
+                stage_row<T, IdxT, true>(st, rs, nA, p.a_col, p.a_val, p.b_rp);
+            }
+            const StEnt<IdxT, true>* ent = st.ent + off;
+            const int L = dpp_reduce_max(lane < nA ? ent[lane].len : 0);
+            const RowGeo rg = row_geo(L, nA);
+            int32_t c[kRowSteps][kLaneEntries];
+            T v[kRowSteps][kLaneEntries];
+            int rem[kRowSteps];
+            double a[kRowSteps];
+            row_loads<T, IdxT, true>(ent, nA, rg, lastB, p.b_col, p.b_val, c, v, rem, a);
+            const int64_t cb = uniform((int64_t)p.c_rp[i]);
+            for (int x = lane; x < kWaveHashSlots; x += kWave) {
+                keys[x] = kEmpty;
+                hv[x] = 0.0;
+            }
+            wave_sync();
 #pragma unroll
-        for (int t = 0; t < MAXIT; ++t) {
-            if (t < uniform_i32(pl.nIt) && ok[t]) {
-                const double v = tb.a[own[t]] * (double)bv[t];
-                const uint32_t key = (uint32_t)col[t];
-                uint32_t h = hash_col(col[t]) >> (32 - 9);
-                while (true) {
-                    const uint32_t old = atomicCAS(&keys[h], kEmpty, key);
-                    if (old == kEmpty || old == key) break;
-                    h = (h + 1) & (kWaveHashSlots - 1);
+            for (int t = 0; t < kRowSteps; ++t) {
+                if (t < rg.S) {
+#pragma unroll
+                    for (int u = 0; u < kLaneEntries; ++u) {
+                        const uint32_t key = slot_col(c, rem, t, u);
+                        if ((int)key >= 0) {
+                            uint32_t hs = hash_col((int)key) >> (32 - 9);
+                            while (true) {
+                                const uint32_t old = atomicCAS(&keys[hs], kEmpty, key);
+                                if (old == kEmpty || old == key) break;
+                                hs = (hs + 1) & (kWaveHashSlots - 1);
+                            }
+                            atomicAdd(&hv[hs], a[t] * (double)v[t][u]);
+                        }
+                    }
                 }
-                atomicAdd(&hv[h], v);
             }
-        }
-        wave_sync();
-        int nc = 0;
-        for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
-            const int x = x0 + lane;
-            const bool occ = keys[x] != kEmpty;
-            const uint64_t bm = ballot(occ);
-            if (occ) {
-                const int pos = nc + mbcnt(bm);
-                ck[pos] = (int32_t)keys[x];
-                cv[pos] = hv[x];
+            wave_sync();
+            int nc = 0;
+            for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
+                const int x = x0 + lane;
+                const bool occ = keys[x] != kEmpty;
+                const uint64_t om = ballot(occ);
+                if (occ && nc + mbcnt(om) < NC) {
+                    const int pos = nc + mbcnt(om);
+                    ck[pos] = (int32_t)keys[x];
+                    cv[pos] = hv[x];
+                }
+                nc += __popcll(om);
             }
-            nc += __popcll(bm);
-        }
-        wave_sync();
-        int key[kWaveHashIt];
-        int rank[kWaveHashIt];
+            nc = min(nc, NC);
+            wave_sync();
+            int key[NCU];
+            int rank[NCU];
 #pragma unroll
-        for (int u = 0; u < kWaveHashIt; ++u) {
-            const int e = u * kWave + lane;
-            key[u] = (e < nc) ? ck[e] : INT32_MAX;
-            rank[u] = 0;
-        }
-        for (int j = 0; j < nc; ++j) {
-            const int kj = ck[j];
-#pragma unroll
-            for (int u = 0; u < kWaveHashIt; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kWaveHashIt; ++u) {
-            const int e = u * kWave + lane;
-            if (e < nc) {
-                p.c_col[(int64_t)cb + rank[u]] = key[u];
-                p.c_val[(int64_t)cb + rank[u]] = (T)cv[e];
+            for (int u = 0; u < NCU; ++u) {
+                const int e = u * kWave + lane;
+                key[u] = (e < nc) ? ck[e] : INT32_MAX;
+                rank[u] = 0;
             }
+            for (int j = 0; j < nc; ++j) {
+                const int kj = ck[j];
+#pragma unroll
+                for (int u = 0; u < NCU; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < NCU; ++u) {
+                const int e = u * kWave + lane;
+                if (e < nc) {
+                    p.c_col[cb + rank[u]] = key[u];
+                    p.c_val[cb + rank[u]] = (T)cv[e];
+                }
+            }
+            wave_sync();
         }
-        wave_sync();
     }
 }
 

@@ -531,6 +531,7 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
         SymArgs<IdxT> a{};
         a.m = ps.m;
         a.n = ps.n;
+        a.k = ps.k;
         a.a_rp = to_gptr(static_cast<const IdxT*>(A[q].row_ptr));
         a.a_col = to_gptr(A[q].col_idx);
         a.b_rp = to_gptr(static_cast<const IdxT*>(B[q].row_ptr));
@@ -772,11 +773,11 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     if (p->agg.cls[kClsWaveBmpS] > 0) {
         if (tab)
             hipLaunchKernelGGL(
-                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS, true>),
+                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, true>),
                 dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
         else
             hipLaunchKernelGGL(
-                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kWaveSmallWords, kWaveSmallIt, kNumWavesS, false>),
+                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, false>),
                 dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_bmp");
@@ -818,6 +819,7 @@ reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_cs
         NumArgs<T, IdxT, IdxC> a{};
         a.m = ps.m;
         a.n = ps.n;
+        a.k = ps.k;
         a.a_rp = to_gptr(static_cast<const IdxT*>(A[q].row_ptr));
         a.a_col = to_gptr(A[q].col_idx);
         a.a_val = to_gptr(static_cast<const T*>(A[q].values));

@@ -26,27 +26,22 @@ __host__ __device__ inline gptr<T> to_gptr(T* p) {
 // Row classes, decided by the symbolic pass from the row's partial-product
 // count P_i, its number of A entries, its column window and nnz(C_i).
 enum RowClass : uint8_t {
-    kClsEmpty = 0,   // P_i = 0: the row of C is empty
-    kClsWaveBmpS = 1,  // one wavefront, window <= kWaveSmallWords words, nnz <= small cap, <= 768 products
-    kClsWaveBmpL = 2,  // not produced (rows past the compact class are long rows)
-    kClsWaveHash = 3,  // one wavefront, LDS hash table (window too wide for a bitmap)
+    kClsEmpty = 0,     // P_i = 0: the row of C is empty
+    kClsWaveBmpS = 1,  // one wavefront, circular LDS bitmap, at most kWaveSmallNnz entries of C
+    kClsWaveBmpL = 2,  // not produced
+    kClsWaveHash = 3,  // one wavefront, LDS hash table (window too wide for the bitmap)
     kClsGroup = 4,     // one workgroup: long rows
     kNumClasses = 5
 };
 
-constexpr int kWaveMaxProducts = 1024;   // products per wavefront row (16 per lane)
-constexpr int kWaveMaxIt = kWaveMaxProducts / 64;
-constexpr int kWaveBitsWords = 1024;     // 32768-column window
-constexpr int kWaveSmallWords = 640;     // 20480-column window for the small numeric class
-constexpr int kWaveSmallNnz = 128;
-constexpr int kWaveSmallProducts = 768;  // products of a small-class row (12 per lane)
-constexpr int kWaveSmallIt = 14;         // 64-lane steps of a small-class row (grouped mapping)
+constexpr int kWaveMaxProducts = 1024;   // product slots of a wavefront row (16 per lane)
+constexpr int kWaveBitsWords = 1024;     // circular bitmap of the wavefront kernels: 32768 columns
+constexpr int kWaveSmallNnz = 128;       // entries of C a wavefront numeric row holds
 constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products
 constexpr int kWaveHashSlots = 512;      // load factor <= 1/2
-constexpr int kWaveHashIt = kWaveHashProducts / 64;
 constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap segment of a long row
 constexpr int kRowsPerWave = 8;          // consecutive rows a wavefront walks through
-constexpr int kStageCap = 256;           // A entries of one chunk of rows staged in LDS
+constexpr int kStageCap = 256;           // A entries of one chunk of rows staged in LDS (symbolic)
 
 // Per-workgroup partial statistics of the wavefront symbolic kernel.
 struct WGPart {
