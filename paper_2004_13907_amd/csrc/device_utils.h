@@ -7,6 +7,10 @@ namespace reap {
 
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+// Word 3 of a raw buffer descriptor on CDNA (gfx9 family): 32-bit data
+// format, no swizzle, no index stride.  Reads past the descriptor's
+// num_records bytes return 0.
+constexpr int kBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

@@ -19,9 +19,15 @@
 // Column sets live in a circular LDS bitmap of kWaveBitsWords 32-bit words
 // indexed by the absolute column (word (col >> 5) mod kWaveBitsWords), which
 // holds any row whose columns span fewer than kBmpMaxWords words: no window
-// offset is subtracted per product.  The numeric pass ranks each column by a
-// prefix count per word taken in window order from the row's first word, so
-// the rank of a column is its position in the sorted row (no sort).
+// offset is subtracted per product.  Word w is stored at position
+// w ^ (((w >> 7) & 3) << 2): the 4-word quads inside each 16-word block are
+// permuted by bits 7-8 of the word, so that words 128 apart (columns 4096
+// apart, the plane stride of a 64^3 stencil) fall in different LDS banks.
+// The numeric pass ranks each column by a prefix count per word taken in
+// window order from the row's first word, so the rank of a column is its
+// position in the sorted row (no sort).  Slots without a product aim at a
+// dummy word (and a dummy accumulator) of their own lane, so the slot loops
+// need no branches and all their LDS reads are issued before any is used.
 #pragma once
 #include "device_utils.h"
 #include "kernels_numeric.h"
@@ -33,7 +39,8 @@ namespace reap {
 constexpr int kLaneEntries = 4;                     // consecutive B entries per lane and step
 constexpr int kRowSteps = kWaveMaxProducts / (kWave * kLaneEntries);  // steps of a wavefront row
 constexpr int kBmpMask = kWaveBitsWords - 1;
-constexpr int kBmpMaxWords = kWaveBitsWords - 8;    // the scan starts at an 8-aligned word
+constexpr int kBmpMaxWords = kWaveBitsWords - 16;   // the scan starts at a 16-aligned word
+constexpr int kBmpAlloc = kWaveBitsWords + kWave;   // plus one dummy word per lane
 constexpr int kNumStageRows = kRowsPerWave / 2;     // rows per staged chunk in the numeric kernels
 constexpr int kNumStageCap = kStageCap / 2;
 
@@ -52,8 +59,8 @@ struct StEnt<IdxT, true> {
 
 template <typename IdxT, bool VALS, int ROWS, int CAP>
 struct ChunkStage {
-    int32_t rowoff[ROWS + 1];   // entries of row r: [rowoff[r], rowoff[r + 1])
-    StEnt<IdxT, VALS> ent[CAP];
+    StEnt<IdxT, VALS> ent[CAP];    // first, so that 16-byte entries stay 16-byte aligned
+    int32_t rowoff[ROWS + 1];      // entries of row r: [rowoff[r], rowoff[r + 1])
 };
 
 // Stages rows [row0, row0 + nrows) (nrows <= ROWS).  Returns false (nothing
@@ -156,49 +163,94 @@ __device__ __forceinline__ RowGeo row_geo(int L, int nA) {
     return r;
 }
 
-// Issues every load of this lane's products of a row: for step t < S the
-// lane's B entries b0 + q0 + u (u < kLaneEntries) of its A entry, rem[t] of
-// which belong to the row (the rest are loaded but never used).  Loads stay
-// inside B: lanes without an entry read from index 0, and a lane whose four
-// entries would pass the last one (lastB) clamps them.
-template <typename T, typename IdxT, bool VALS>
-__device__ __forceinline__ void row_loads(const StEnt<IdxT, VALS>* ent, int nA, const RowGeo& rg, IdxT lastB,
-                                          const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
-                                          int32_t (&c)[kRowSteps][kLaneEntries], T (&v)[kRowSteps][kLaneEntries],
-                                          int (&rem)[kRowSteps], double (&a)[kRowSteps]) {
+// Reads of B's entries, kLaneEntries consecutive ones per call.  With BUF the
+// reads are raw buffer loads through descriptors whose range is B's arrays:
+// 32-bit byte offsets, and the hardware returns 0 for entries past the end
+// of B instead of faulting, so a lane's four reads need no clamp (the host
+// selects BUF when B's values take fewer than 2^31 bytes).  Without BUF the
+// reads are global loads, and a lane whose four entries would pass B's last
+// entry clamps them.
+template <typename T, bool BUF>
+struct BReader;
+
+template <typename T>
+struct BReader<T, true> {
+    __amdgpu_buffer_rsrc_t col, val;
+    __device__ __forceinline__ BReader(const int32_t* c, const T* v, int64_t nnz) {
+        col = __builtin_amdgcn_make_buffer_rsrc((void*)c, (short)0, (int)(nnz * 4), kBufferWord3);
+        val = __builtin_amdgcn_make_buffer_rsrc((void*)v, (short)0, (int)(nnz * (int64_t)sizeof(T)), kBufferWord3);
+    }
+    template <bool VALS>
+    __device__ __forceinline__ void load(int64_t base, int32_t (&c)[kLaneEntries], T (&v)[kLaneEntries]) const {
+        const int oc = (int)base * 4;
 #pragma unroll
-    for (int t = 0; t < kRowSteps; ++t) {
-        rem[t] = 0;
-        a[t] = 0.0;
-        if (t < rg.S) {
-            const int e = rg.g * rg.S + t;
-            const bool act = rg.g < rg.E && e < nA;
-            const StEnt<IdxT, VALS> en = ent[act ? e : 0];
-            rem[t] = act ? en.len - rg.q0 : 0;
-            if constexpr (VALS) a[t] = en.a;
-            const IdxT base = act ? en.b0 + (IdxT)rg.q0 : (IdxT)0;
-            if (base + (IdxT)(kLaneEntries - 1) <= lastB) {
+        for (int u = 0; u < kLaneEntries; ++u) c[u] = __builtin_amdgcn_raw_buffer_load_b32(col, oc + 4 * u, 0, 0);
+        if constexpr (VALS) {
+            const int ov = (int)base * (int)sizeof(T);
 #pragma unroll
-                for (int u = 0; u < kLaneEntries; ++u) {
-                    c[t][u] = b_col[base + u];
-                    if (VALS) v[t][u] = b_val[base + u];
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < kLaneEntries; ++u) {
-                    const IdxT idx = min(base + (IdxT)u, lastB);
-                    c[t][u] = b_col[idx];
-                    if (VALS) v[t][u] = b_val[idx];
-                }
+            for (int u = 0; u < kLaneEntries; ++u) {
+                if constexpr (sizeof(T) == 8)
+                    v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(val, ov + 8 * u, 0, 0));
+                else
+                    v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(val, ov + 4 * u, 0, 0));
             }
         }
     }
+};
+
+template <typename T>
+struct BReader<T, false> {
+    const int32_t* col;
+    const T* val;
+    int64_t last;
+    __device__ __forceinline__ BReader(const int32_t* c, const T* v, int64_t nnz) : col(c), val(v), last(nnz - 1) {}
+    template <bool VALS>
+    __device__ __forceinline__ void load(int64_t base, int32_t (&c)[kLaneEntries], T (&v)[kLaneEntries]) const {
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u) {
+            const int64_t idx = min(base + u, last);
+            c[u] = col[idx];
+            if (VALS) v[u] = val[idx];
+        }
+    }
+};
+
+// Issues every load of this lane's products of a row of S steps: for step t
+// the lane's B entries b0 + q0 + u (u < kLaneEntries) of its A entry, rem[t]
+// of which belong to the row (the rest are read but never used; lanes
+// without an entry read entries 0..3).
+template <int S, typename T, typename IdxT, bool VALS, bool BUF>
+__device__ __forceinline__ void row_loads(const StEnt<IdxT, VALS>* ent, int nA, const RowGeo& rg,
+                                          const BReader<T, BUF>& br, int32_t (&c)[S][kLaneEntries],
+                                          T (&v)[S][kLaneEntries], int (&rem)[S], double (&a)[S]) {
+    StEnt<IdxT, VALS> en[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) en[t] = ent[min(rg.g * S + t, nA - 1)];
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        const bool act = rg.g < rg.E && rg.g * S + t < nA;
+        rem[t] = act ? en[t].len - rg.q0 : 0;
+        a[t] = 0.0;
+        if constexpr (VALS) a[t] = en[t].a;
+        br.template load<VALS>(act ? (int64_t)en[t].b0 + rg.q0 : (int64_t)0, c[t], v[t]);
+    }
 }
 
-// Column of slot (t, u), or 0xFFFFFFFF when the slot holds no product.
-__device__ __forceinline__ uint32_t slot_col(const int32_t (&c)[kRowSteps][kLaneEntries], const int (&rem)[kRowSteps],
-                                             int t, int u) {
-    return u < rem[t] ? (uint32_t)c[t][u] : 0xFFFFFFFFu;
+// Circular-bitmap position of slot (t, u): the word of its column (see the
+// file comment), or this lane's dummy word when the slot holds no product.
+template <int S>
+__device__ __forceinline__ void slot_positions(const int32_t (&c)[S][kLaneEntries], const int (&rem)[S],
+                                               int (&pos)[S][kLaneEntries]) {
+    const int dummy = kWaveBitsWords + lane_id();
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u) {
+            const uint32_t cc = (uint32_t)c[t][u];
+            const int ps = (int)(((cc >> 5) & kBmpMask) ^ ((cc >> 10) & 12u));
+            pos[t][u] = u < rem[t] ? ps : dummy;
+        }
+    }
 }
 
 // Clears the circular bitmap: four 16-byte stores per lane, lanes side by side.
@@ -208,8 +260,13 @@ __device__ __forceinline__ void bmp_clear(uint32_t* bits) {
         *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane_id())) = make_uint4(0u, 0u, 0u, 0u);
 }
 
-__device__ __forceinline__ void bmp_set(uint32_t* bits, uint32_t col) {
-    atomicOr(&bits[(col >> 5) & kBmpMask], 1u << (col & 31));
+template <int S>
+__device__ __forceinline__ void bmp_or(uint32_t* bits, const int32_t (&c)[S][kLaneEntries],
+                                       const int (&pos)[S][kLaneEntries]) {
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u) atomicOr(&bits[pos[t][u]], 1u << (c[t][u] & 31));
 }
 
 // Set bits of the whole bitmap, summed over the wavefront.
@@ -223,6 +280,75 @@ __device__ __forceinline__ int bmp_count(const uint32_t* bits) {
     return dpp_reduce_sum(pc);
 }
 
+// Symbolic work of one row of S steps: column window, then the distinct
+// columns counted with the bitmap (or a hash set when the window is too wide).
+template <int S, typename IdxT, bool BUF>
+__device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, int P, const RowGeo& rg,
+                                        const BReader<float, BUF>& br, uint32_t* bits, const Thresholds& th,
+                                        uint8_t& cls, int& nnz, int2& win) {
+    const int lane = lane_id();
+    int32_t c[S][kLaneEntries];
+    float v_unused[S][kLaneEntries];
+    int rem[S];
+    double a_unused[S];
+    row_loads<S, float, IdxT, false, BUF>(ent, nA, rg, br, c, v_unused, rem, a_unused);
+    uint32_t cmin = 0xFFFFFFFFu;
+    int cmax = -1;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u) {
+            const uint32_t cc = u < rem[t] ? (uint32_t)c[t][u] : 0xFFFFFFFFu;
+            cmin = min(cmin, cc);
+            cmax = max(cmax, (int)cc);
+        }
+    }
+    cmin = wave_reduce(cmin, [](uint32_t x, uint32_t y) { return min(x, y); });
+    cmax = dpp_reduce_max(cmax);
+    const int nw = (cmax >> 5) - (int)(cmin >> 5) + 1;
+    if (nw <= kBmpMaxWords && (int64_t)cmax - (int64_t)cmin + 1 <= (int64_t)th.wave_max_span) {
+        int pos[S][kLaneEntries];
+        slot_positions<S>(c, rem, pos);
+        bmp_clear(bits);
+        wave_sync();
+        bmp_or<S>(bits, c, pos);
+        wave_sync();
+        nnz = bmp_count(bits);
+        win = make_int2((int)cmin, nw);
+        cls = nnz <= th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
+    } else if (P <= th.wave_hash_products) {
+        // an LDS hash set of the row's columns (the bitmap area, kWaveHashSlots keys)
+#pragma unroll
+        for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)
+            *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) =
+                make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        wave_sync();
+        int mine = 0;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+#pragma unroll
+            for (int u = 0; u < kLaneEntries; ++u) {
+                const uint32_t key = (uint32_t)c[t][u];
+                if (u < rem[t]) {
+                    uint32_t h = hash_col((int)key) >> (32 - 9);
+                    while (true) {
+                        const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
+                        if (old == 0xFFFFFFFFu) {
+                            ++mine;
+                            break;
+                        }
+                        if (old == key) break;
+                        h = (h + 1) & (kWaveHashSlots - 1);
+                    }
+                }
+            }
+        }
+        nnz = dpp_reduce_sum(mine);
+        cls = kClsWaveHash;
+    }
+    wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // Symbolic, one wavefront per row.  Classifies every row and counts the
 // distinct columns of rows that stay here: the circular LDS bitmap when the
@@ -233,11 +359,11 @@ __device__ __forceinline__ int bmp_count(const uint32_t* bits) {
 // th.wave_max_products products, or more entries of C than the wavefront
 // numeric kernels hold go to the long-row list.
 // TAB: arguments from the batch table (else the by-value argument of a single product).
-template <typename IdxT, bool TAB>
+template <typename IdxT, bool TAB, bool BUF>
 __global__ void __launch_bounds__(kWaveKernelWaves * 64)
 k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     constexpr int W = kWaveKernelWaves;
-    __shared__ __align__(16) uint32_t s_bits[W][kWaveBitsWords];
+    __shared__ __align__(16) uint32_t s_bits[W][kBmpAlloc];
     __shared__ __align__(16) ChunkStage<IdxT, false, kRowsPerWave, kStageCap> s_stage[W];
     __shared__ WGPart s_part[W];
 
@@ -263,7 +389,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool staged = nrows > 0 && stage_chunk<float, IdxT, false>(st, row0, nrows, p.a_rp, p.a_col,
                                                                         (const float*)nullptr, p.b_rp);
-    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
+    const BReader<float, BUF> br(p.b_col, nullptr, (int64_t)uniform(p.b_rp[p.k]));
 
     for (int r = 0; r < nrows; ++r) {
         const int64_t i = row0 + r;
@@ -292,77 +418,12 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
             if (P == 0) {
                 cls = kClsEmpty;
             } else if (fits && rg.S <= kRowSteps) {
-                int32_t c[kRowSteps][kLaneEntries];
-                float v_unused[kRowSteps][kLaneEntries];
-                int rem[kRowSteps];
-                double a_unused[kRowSteps];
-                row_loads<float, IdxT, false>(ent, nA, rg, lastB, p.b_col, nullptr, c, v_unused, rem, a_unused);
-                uint32_t cmin = 0xFFFFFFFFu;
-                int cmax = -1;
-#pragma unroll
-                for (int t = 0; t < kRowSteps; ++t) {
-                    if (t < rg.S) {
-#pragma unroll
-                        for (int u = 0; u < kLaneEntries; ++u) {
-                            const uint32_t cc = slot_col(c, rem, t, u);
-                            cmin = min(cmin, cc);
-                            cmax = max(cmax, (int)cc);
-                        }
-                    }
+                switch (rg.S) {
+                    case 1: sym_row<1, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
+                    case 2: sym_row<2, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
+                    case 3: sym_row<3, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
+                    default: sym_row<4, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
                 }
-                cmin = wave_reduce(cmin, [](uint32_t x, uint32_t y) { return min(x, y); });
-                cmax = dpp_reduce_max(cmax);
-                const int nw = (cmax >> 5) - (int)(cmin >> 5) + 1;
-                if (nw <= kBmpMaxWords && (int64_t)cmax - (int64_t)cmin + 1 <= (int64_t)p.th.wave_max_span) {
-                    bmp_clear(bits);
-                    wave_sync();
-#pragma unroll
-                    for (int t = 0; t < kRowSteps; ++t) {
-                        if (t < rg.S) {
-#pragma unroll
-                            for (int u = 0; u < kLaneEntries; ++u) {
-                                const uint32_t cc = slot_col(c, rem, t, u);
-                                if ((int)cc >= 0) bmp_set(bits, cc);
-                            }
-                        }
-                    }
-                    wave_sync();
-                    nnz = bmp_count(bits);
-                    win = make_int2((int)cmin, nw);
-                    cls = nnz <= p.th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
-                } else if (P <= p.th.wave_hash_products) {
-                    // an LDS hash set of the row's columns (the bitmap area, kWaveHashSlots keys)
-#pragma unroll
-                    for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)
-                        *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) =
-                            make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-                    wave_sync();
-                    int mine = 0;
-#pragma unroll
-                    for (int t = 0; t < kRowSteps; ++t) {
-                        if (t < rg.S) {
-#pragma unroll
-                            for (int u = 0; u < kLaneEntries; ++u) {
-                                const uint32_t key = slot_col(c, rem, t, u);
-                                if ((int)key >= 0) {
-                                    uint32_t h = hash_col((int)key) >> (32 - 9);
-                                    while (true) {
-                                        const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
-                                        if (old == 0xFFFFFFFFu) {
-                                            ++mine;
-                                            break;
-                                        }
-                                        if (old == key) break;
-                                        h = (h + 1) & (kWaveHashSlots - 1);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                    nnz = dpp_reduce_sum(mine);
-                    cls = kClsWaveHash;
-                }
-                wave_sync();
                 if (cls != kClsGroup) {
                     prod_acc += (unsigned long long)P;
                     maxp = max(maxp, (unsigned)P);
@@ -417,28 +478,121 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     }
 }
 
+// LDS of one wavefront of the compact bitmap numeric kernel.
+template <typename IdxT, int NCMAX>
+struct NumBmpLds {
+    uint32_t bits[kBmpAlloc];     // circular bitmap (+ a dummy word per lane)
+    uint8_t pfx[kBmpAlloc];       // entries of the row before each word (8 bits: rows hold < 256)
+    double vals[NCMAX + kWave];   // accumulators by rank (+ a dummy per lane)
+    int32_t cols[NCMAX + kWave];  // columns by rank
+    ChunkStage<IdxT, true, kNumStageRows, kNumStageCap> st;
+};
+
+// Numeric work of one compact-class row of S steps.
+template <int S, typename T, typename IdxT, typename IdxC, int NCMAX, bool BUF>
+__device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int64_t i,
+                                            const StEnt<IdxT, true>* ent, int nA, const RowGeo& rg,
+                                            const BReader<T, BUF>& br, NumBmpLds<IdxT, NCMAX>& sh) {
+    const int lane = lane_id();
+    int32_t c[S][kLaneEntries];
+    T v[S][kLaneEntries];
+    int rem[S];
+    double a[S];
+    row_loads<S, T, IdxT, true, BUF>(ent, nA, rg, br, c, v, rem, a);
+    const int2 wn = p.win[i];
+    const int lo_w = uniform_i32(wn.x) >> 5;
+    const int64_t cb = uniform((int64_t)p.c_rp[i]);
+    const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
+    bmp_clear(sh.bits);
+    for (int x = lane; x < nc; x += kWave) sh.vals[x] = 0.0;
+    int pos[S][kLaneEntries];
+    slot_positions<S>(c, rem, pos);
+    wave_sync();
+    bmp_or<S>(sh.bits, c, pos);
+    wave_sync();
+    // prefix counts in window order, in four rounds of 256 words: in round j
+    // lane l takes word quad s0/4 + 64 j + l (s0 the row's first word
+    // rounded down to 16), so that the lanes' 16-byte reads and 4-byte writes
+    // are side by side in LDS; a wavefront scan gives each quad its prefix.
+    {
+        const int q0 = ((lo_w & kBmpMask) & ~15) >> 2;   // first quad of the window
+        int carry = 0;
+#pragma unroll
+        for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j) {
+            const int qd = (q0 + j * kWave + lane) & (kBmpMask >> 2);   // quad in word order
+            const int qp = qd ^ ((qd >> 5) & 3);                        // its position (see bmp_pos)
+            const uint4 qv = *reinterpret_cast<const uint4*>(sh.bits + 4 * qp);
+            const int c0 = __popc(qv.x), c1 = __popc(qv.y), c2 = __popc(qv.z), c3 = __popc(qv.w);
+            const int tot = c0 + c1 + c2 + c3;
+            const int incl = dpp_incl_scan(tot);
+            const int r0 = carry + incl - tot;
+            carry += __builtin_amdgcn_readlane(incl, kWave - 1);
+            const uint32_t pk = (uint32_t)(r0 & 0xFF) | ((uint32_t)((r0 + c0) & 0xFF) << 8) |
+                                ((uint32_t)((r0 + c0 + c1) & 0xFF) << 16) |
+                                ((uint32_t)((r0 + c0 + c1 + c2) & 0xFF) << 24);
+            *reinterpret_cast<uint32_t*>(sh.pfx + 4 * qp) = pk;
+        }
+    }
+    wave_sync();
+    // ranks, two steps at a time, the reads of both issued before any is
+    // used; a slot without a product reads its lane's dummy word, whose
+    // prefix byte (255) puts its rank out of range
+#pragma unroll
+    for (int t0 = 0; t0 < S; t0 += 2) {
+        constexpr int H = 2;
+        uint32_t rword[H][kLaneEntries];
+        uint32_t rpfx[H][kLaneEntries];
+#pragma unroll
+        for (int dt = 0; dt < H; ++dt)
+            if (t0 + dt < S)
+#pragma unroll
+                for (int u = 0; u < kLaneEntries; ++u) {
+                    rword[dt][u] = sh.bits[pos[t0 + dt][u]];
+                    rpfx[dt][u] = sh.pfx[pos[t0 + dt][u]];
+                }
+#pragma unroll
+        for (int dt = 0; dt < H; ++dt) {
+            const int t = t0 + dt;
+            if (t < S) {
+#pragma unroll
+                for (int u = 0; u < kLaneEntries; ++u) {
+                    // bits of the word below the column (width taken mod 32 by the instruction)
+                    const uint32_t below = __builtin_amdgcn_ubfe(rword[dt][u], 0u, (uint32_t)c[t][u]);
+                    const int rk0 = (int)(rpfx[dt][u] & 0xFFu) + __popc(below);
+                    // rk0 < nc for every product whenever the pattern matches the symbolic pass
+                    const int rk = rk0 < nc ? rk0 : NCMAX + lane;
+                    atomicAdd(&sh.vals[rk], a[t] * (double)v[t][u]);
+                    sh.cols[rk] = c[t][u];
+                }
+            }
+        }
+    }
+    wave_sync();
+    for (int x = lane; x < nc; x += kWave) {
+        p.c_col[cb + x] = sh.cols[x];
+        p.c_val[cb + x] = (T)sh.vals[x];
+    }
+    wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // Numeric, one wavefront per row of the compact bitmap class (at most NCMAX
 // entries of C, columns spanning fewer than kBmpMaxWords words): products
 // held in registers, circular bitmap of the row's columns, per-word prefix
 // counts in window order, each product added into the LDS slot of its
-// column's rank, the row written in ascending column order.
-template <typename T, typename IdxT, typename IdxC, int NCMAX, int W, bool TAB>
-__global__ void __launch_bounds__(W * 64)
+// column's rank, the row written in ascending column order.  Each wavefront
+// walks the kRowsPerWave rows of its symbolic chunk, staged in halves.
+template <typename T, typename IdxT, typename IdxC, int NCMAX, int W, bool TAB, bool BUF>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
 k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
-    __shared__ __align__(16) uint32_t s_bits[W][kWaveBitsWords];
-    __shared__ __align__(16) uint16_t s_pfx[W][kWaveBitsWords];
-    __shared__ double s_vals[W][NCMAX + 1];
-    __shared__ int32_t s_cols[W][NCMAX + 1];
-    __shared__ __align__(16) ChunkStage<IdxT, true, kNumStageRows, kNumStageCap> s_stage[W];
+    static_assert(NCMAX < 255, "prefix counts are stored in 8 bits, 255 marks a dummy word");
+    __shared__ __align__(16) NumBmpLds<IdxT, NCMAX> s_lds[W];
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    uint32_t* bits = s_bits[w];
-    uint16_t* pfx = s_pfx[w];
-    double* vals = s_vals[w];
-    int32_t* cols_l = s_cols[w];
-    auto& st = s_stage[w];
+    NumBmpLds<IdxT, NCMAX>& sh = s_lds[w];
+    auto& st = sh.st;
+    sh.pfx[kWaveBitsWords + lane] = 0xFF;   // dummy words: ranks out of range
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
@@ -448,7 +602,7 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
     const int nall = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - rowc));
     const uint64_t todo_all = ballot(lane < nall && p.cls[rowc + lane] == want);
     if (!todo_all) return;
-    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
+    const BReader<T, BUF> br(p.b_col, p.b_val, (int64_t)uniform(p.b_rp[p.k]));
 
     for (int h = 0; h < kRowsPerWave / kNumStageRows; ++h) {
         const int64_t row0 = rowc + h * kNumStageRows;
@@ -473,97 +627,101 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
             const StEnt<IdxT, true>* ent = st.ent + off;
             const int L = dpp_reduce_max(lane < nA ? ent[lane].len : 0);
             const RowGeo rg = row_geo(L, nA);
-            int32_t c[kRowSteps][kLaneEntries];
-            T v[kRowSteps][kLaneEntries];
-            int rem[kRowSteps];
-            double a[kRowSteps];
-            row_loads<T, IdxT, true>(ent, nA, rg, lastB, p.b_col, p.b_val, c, v, rem, a);
-            const int2 wn = p.win[i];
-            const int lo_w = uniform_i32(wn.x) >> 5;
-            const int64_t cb = uniform((int64_t)p.c_rp[i]);
-            const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
-            bmp_clear(bits);
-            for (int x = lane; x < nc; x += kWave) vals[x] = 0.0;
-            wave_sync();
-#pragma unroll
-            for (int t = 0; t < kRowSteps; ++t) {
-                if (t < rg.S) {
-#pragma unroll
-                    for (int u = 0; u < kLaneEntries; ++u) {
-                        const uint32_t cc = slot_col(c, rem, t, u);
-                        if ((int)cc >= 0) bmp_set(bits, cc);
-                    }
-                }
+            switch (rg.S) {
+                case 1: num_row_bmp<1, T, IdxT, IdxC, NCMAX, BUF>(p, i, ent, nA, rg, br, sh); break;
+                case 2: num_row_bmp<2, T, IdxT, IdxC, NCMAX, BUF>(p, i, ent, nA, rg, br, sh); break;
+                case 3: num_row_bmp<3, T, IdxT, IdxC, NCMAX, BUF>(p, i, ent, nA, rg, br, sh); break;
+                default: num_row_bmp<4, T, IdxT, IdxC, NCMAX, BUF>(p, i, ent, nA, rg, br, sh); break;
             }
-            wave_sync();
-            // prefix counts in window order: lane l owns the 16 words from
-            // s0 + 16 l (circularly), s0 the row's first word rounded down to 8
-            {
-                const int s0 = (lo_w & kBmpMask) & ~7;
-                const int wb = (s0 + 16 * lane) & kBmpMask;
-                uint32_t wd[16];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint4 qv = *reinterpret_cast<const uint4*>(bits + ((wb + 4 * k) & kBmpMask));
-                    wd[4 * k] = qv.x;
-                    wd[4 * k + 1] = qv.y;
-                    wd[4 * k + 2] = qv.z;
-                    wd[4 * k + 3] = qv.w;
-                }
-                int local = 0;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) local += __popc(wd[k]);
-                int run = dpp_incl_scan(local) - local;
-                uint32_t pk[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int r0 = run;
-                    run += __popc(wd[2 * k]);
-                    pk[k] = (uint32_t)r0 | ((uint32_t)run << 16);
-                    run += __popc(wd[2 * k + 1]);
-                }
-                uint32_t* pfx32 = reinterpret_cast<uint32_t*>(pfx);
-                *reinterpret_cast<uint4*>(pfx32 + wb / 2) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-                *reinterpret_cast<uint4*>(pfx32 + ((wb + 8) & kBmpMask) / 2) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-            }
-            wave_sync();
-#pragma unroll
-            for (int t = 0; t < kRowSteps; ++t) {
-                if (t < rg.S) {
-#pragma unroll
-                    for (int u = 0; u < kLaneEntries; ++u) {
-                        const uint32_t cc = slot_col(c, rem, t, u);
-                        if ((int)cc >= 0) {
-                            const int wi = (int)((cc >> 5) & kBmpMask);
-                            const uint32_t below = (1u << (cc & 31)) - 1u;
-                            int rk = (int)pfx[wi] + __popc(bits[wi] & below);
-                            rk = rk < nc ? rk : NCMAX;  // rk < nc whenever the pattern matches the symbolic pass
-                            atomicAdd(&vals[rk], a[t] * (double)v[t][u]);
-                            cols_l[rk] = (int32_t)cc;
-                        }
-                    }
-                }
-            }
-            wave_sync();
-            for (int x = lane; x < nc; x += kWave) {
-                p.c_col[cb + x] = cols_l[x];
-                p.c_val[cb + x] = (T)vals[x];
-            }
-            wave_sync();
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// Numeric, one wavefront per row whose columns span too wide a window for the
-// bitmap (at most kWaveHashProducts products): LDS hash table keyed by
+// Numeric work of one hash-class row of S steps: LDS hash table keyed by
 // column, then the occupied slots are compacted and each entry is placed by
 // counting the smaller columns.
-template <typename T, typename IdxT, typename IdxC, int W, bool TAB>
+template <int S, typename T, typename IdxT, typename IdxC, bool BUF>
+__device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, int64_t i,
+                                             const StEnt<IdxT, true>* ent, int nA, const RowGeo& rg,
+                                             const BReader<T, BUF>& br, uint32_t* keys, double* hv, int32_t* ck,
+                                             double* cv) {
+    constexpr int NC = kWaveHashProducts;
+    constexpr int NCU = NC / kWave;
+    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+    const int lane = lane_id();
+    int32_t c[S][kLaneEntries];
+    T v[S][kLaneEntries];
+    int rem[S];
+    double a[S];
+    row_loads<S, T, IdxT, true, BUF>(ent, nA, rg, br, c, v, rem, a);
+    const int64_t cb = uniform((int64_t)p.c_rp[i]);
+    for (int x = lane; x < kWaveHashSlots; x += kWave) {
+        keys[x] = kEmpty;
+        hv[x] = 0.0;
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u) {
+            if (u < rem[t]) {
+                const uint32_t key = (uint32_t)c[t][u];
+                uint32_t hs = hash_col((int)key) >> (32 - 9);
+                while (true) {
+                    const uint32_t old = atomicCAS(&keys[hs], kEmpty, key);
+                    if (old == kEmpty || old == key) break;
+                    hs = (hs + 1) & (kWaveHashSlots - 1);
+                }
+                atomicAdd(&hv[hs], a[t] * (double)v[t][u]);
+            }
+        }
+    }
+    wave_sync();
+    int nc = 0;
+    for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
+        const int x = x0 + lane;
+        const bool occ = keys[x] != kEmpty;
+        const uint64_t om = ballot(occ);
+        if (occ && nc + mbcnt(om) < NC) {
+            const int pos = nc + mbcnt(om);
+            ck[pos] = (int32_t)keys[x];
+            cv[pos] = hv[x];
+        }
+        nc += __popcll(om);
+    }
+    nc = min(nc, NC);
+    wave_sync();
+    int key[NCU];
+    int rank[NCU];
+#pragma unroll
+    for (int u = 0; u < NCU; ++u) {
+        const int e = u * kWave + lane;
+        key[u] = (e < nc) ? ck[e] : INT32_MAX;
+        rank[u] = 0;
+    }
+    for (int j = 0; j < nc; ++j) {
+        const int kj = ck[j];
+#pragma unroll
+        for (int u = 0; u < NCU; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < NCU; ++u) {
+        const int e = u * kWave + lane;
+        if (e < nc) {
+            p.c_col[cb + rank[u]] = key[u];
+            p.c_val[cb + rank[u]] = (T)cv[e];
+        }
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Numeric, one wavefront per row whose columns span too wide a window for the
+// bitmap (at most kWaveHashProducts products).
+template <typename T, typename IdxT, typename IdxC, int W, bool TAB, bool BUF>
 __global__ void __launch_bounds__(W * 64)
 k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
     constexpr int NC = kWaveHashProducts;
-    constexpr int NCU = NC / kWave;
     __shared__ __align__(16) uint32_t s_keys[W][kWaveHashSlots];
     __shared__ double s_hv[W][kWaveHashSlots];
     __shared__ int32_t s_ck[W][NC];
@@ -572,12 +730,7 @@ k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restr
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    uint32_t* keys = s_keys[w];
-    double* hv = s_hv[w];
-    int32_t* ck = s_ck[w];
-    double* cv = s_cv[w];
     auto& st = s_stage[w];
-    constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
@@ -587,7 +740,7 @@ k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restr
     const int nall = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - rowc));
     const uint64_t todo_all = ballot(lane < nall && p.cls[rowc + lane] == want);
     if (!todo_all) return;
-    const IdxT lastB = uniform(p.b_rp[p.k]) - (IdxT)1;
+    const BReader<T, BUF> br(p.b_col, p.b_val, (int64_t)uniform(p.b_rp[p.k]));
 
     for (int h = 0; h < kRowsPerWave / kNumStageRows; ++h) {
         const int64_t row0 = rowc + h * kNumStageRows;
@@ -612,72 +765,14 @@ k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restr
             const StEnt<IdxT, true>* ent = st.ent + off;
             const int L = dpp_reduce_max(lane < nA ? ent[lane].len : 0);
             const RowGeo rg = row_geo(L, nA);
-            int32_t c[kRowSteps][kLaneEntries];
-            T v[kRowSteps][kLaneEntries];
-            int rem[kRowSteps];
-            double a[kRowSteps];
-            row_loads<T, IdxT, true>(ent, nA, rg, lastB, p.b_col, p.b_val, c, v, rem, a);
-            const int64_t cb = uniform((int64_t)p.c_rp[i]);
-            for (int x = lane; x < kWaveHashSlots; x += kWave) {
-                keys[x] = kEmpty;
-                hv[x] = 0.0;
+            uint32_t* keys = s_keys[w];
+            double* hv = s_hv[w];
+            switch (rg.S) {
+                case 1: num_row_hash<1, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
+                case 2: num_row_hash<2, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
+                case 3: num_row_hash<3, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
+                default: num_row_hash<4, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
             }
-            wave_sync();
-#pragma unroll
-            for (int t = 0; t < kRowSteps; ++t) {
-                if (t < rg.S) {
-#pragma unroll
-                    for (int u = 0; u < kLaneEntries; ++u) {
-                        const uint32_t key = slot_col(c, rem, t, u);
-                        if ((int)key >= 0) {
-                            uint32_t hs = hash_col((int)key) >> (32 - 9);
-                            while (true) {
-                                const uint32_t old = atomicCAS(&keys[hs], kEmpty, key);
-                                if (old == kEmpty || old == key) break;
-                                hs = (hs + 1) & (kWaveHashSlots - 1);
-                            }
-                            atomicAdd(&hv[hs], a[t] * (double)v[t][u]);
-                        }
-                    }
-                }
-            }
-            wave_sync();
-            int nc = 0;
-            for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
-                const int x = x0 + lane;
-                const bool occ = keys[x] != kEmpty;
-                const uint64_t om = ballot(occ);
-                if (occ && nc + mbcnt(om) < NC) {
-                    const int pos = nc + mbcnt(om);
-                    ck[pos] = (int32_t)keys[x];
-                    cv[pos] = hv[x];
-                }
-                nc += __popcll(om);
-            }
-            nc = min(nc, NC);
-            wave_sync();
-            int key[NCU];
-            int rank[NCU];
-#pragma unroll
-            for (int u = 0; u < NCU; ++u) {
-                const int e = u * kWave + lane;
-                key[u] = (e < nc) ? ck[e] : INT32_MAX;
-                rank[u] = 0;
-            }
-            for (int j = 0; j < nc; ++j) {
-                const int kj = ck[j];
-#pragma unroll
-                for (int u = 0; u < NCU; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < NCU; ++u) {
-                const int e = u * kWave + lane;
-                if (e < nc) {
-                    p.c_col[cb + rank[u]] = key[u];
-                    p.c_val[cb + rank[u]] = (T)cv[e];
-                }
-            }
-            wave_sync();
         }
     }
 }

@@ -108,6 +108,7 @@ struct reap_spgemm_s {
     double* gvals_ptr = nullptr;   // accumulators in use: gvals.base, or inside the static scratch
     bool ws_static = false;        // the workspace pointers below point into the static scratch
     bool eager = false;            // this call runs its kernels directly (no tables, no graphs)
+    bool buf_b = true;             // every B's values fit 2^31 bytes: buffer loads in the wavefront kernels
     Workspace tws;     // scratch of the device transpose
     int64_t cap_rows = -1, cap_prods = 0;
     int32_t cap_blocks = 0, cap_tiles = 0;
@@ -461,12 +462,15 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
 
     ev_record(p, kPhSymbolic, false);
     if (p->total_blocks > 0) {
-        if (tab)
-            hipLaunchKernelGGL((k_sym_wave<IdxT, true>), dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0,
-                               p->stream, a0, P, bm);
+        const dim3 grid(p->total_blocks), block(kWaveKernelWaves * kWave);
+        if (tab && p->buf_b)
+            hipLaunchKernelGGL((k_sym_wave<IdxT, true, true>), grid, block, 0, p->stream, a0, P, bm);
+        else if (tab)
+            hipLaunchKernelGGL((k_sym_wave<IdxT, true, false>), grid, block, 0, p->stream, a0, P, bm);
+        else if (p->buf_b)
+            hipLaunchKernelGGL((k_sym_wave<IdxT, false, true>), grid, block, 0, p->stream, a0, P, bm);
         else
-            hipLaunchKernelGGL((k_sym_wave<IdxT, false>), dim3(p->total_blocks), dim3(kWaveKernelWaves * kWave), 0,
-                               p->stream, a0, P, bm);
+            hipLaunchKernelGGL((k_sym_wave<IdxT, false, false>), grid, block, 0, p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
         // the long-row count is known on the device only: a fixed grid takes rows from the list
@@ -586,7 +590,7 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
     if (!p->use_graph || p->eager) return launch_symbolic<IdxT>(p, a0, s0);
     std::vector<uint64_t> key = {p->ws_generation, (uint64_t)nprod, (uint64_t)p->total_blocks,
                                  (uint64_t)p->total_tiles, (uint64_t)p->total_rows, (uint64_t)p->cidx,
-                                 (uint64_t)sizeof(IdxT)};
+                                 (uint64_t)sizeof(IdxT), (uint64_t)p->buf_b};
     return run_pass(p, p->g_sym, p->g_sym_key, key, [&]() { return launch_symbolic<IdxT>(p, a0, s0); });
 }
 
@@ -676,6 +680,9 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     p->total_rows = ro;
     p->total_blocks = bo;
     p->total_tiles = to;
+    // buffer loads take 32-bit byte offsets: B's values must stay below 2^31 bytes
+    p->buf_b = true;
+    for (int64_t q = 0; q < count; ++q) p->buf_b &= B[q].nnz < ((int64_t)1 << 28);
 
     st = (in_idx == REAP_I32) ? symbolic_typed<int32_t>(p, A, B, c_row_ptr)
                               : symbolic_typed<int64_t>(p, A, B, c_row_ptr);
@@ -771,26 +778,40 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     ev_record(p, kPhNumAll, false);
     ev_record(p, kPhNumWave, false);
     if (p->agg.cls[kClsWaveBmpS] > 0) {
-        if (tab)
-            hipLaunchKernelGGL(
-                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, true>),
-                dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
+        const dim3 grid(p->total_blocks), block(kNumWavesS * kWave);
+        const uint8_t want = kClsWaveBmpS;
+        if (tab && p->buf_b)
+            hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, true, true>), grid, block,
+                               0, p->stream, a0, P, bm, want);
+        else if (tab)
+            hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, true, false>), grid, block,
+                               0, p->stream, a0, P, bm, want);
+        else if (p->buf_b)
+            hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, false, true>), grid, block,
+                               0, p->stream, a0, P, bm, want);
         else
-            hipLaunchKernelGGL(
-                (k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, false>),
-                dim3(p->total_blocks), dim3(kNumWavesS * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveBmpS);
+            hipLaunchKernelGGL((k_num_wave_bmp<T, IdxT, IdxC, kWaveSmallNnz, kNumWavesS, false, false>), grid, block,
+                               0, p->stream, a0, P, bm, want);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_bmp");
     }
     ev_record(p, kPhNumWave, true);
     ev_record(p, kPhNumHash, false);
     if (p->agg.cls[kClsWaveHash] > 0) {
-        if (tab)
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true>), dim3(p->total_blocks),
-                               dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
+        const dim3 grid(p->total_blocks), block(kNumWavesH * kWave);
+        const uint8_t want = kClsWaveHash;
+        if (tab && p->buf_b)
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, true>), grid, block, 0, p->stream,
+                               a0, P, bm, want);
+        else if (tab)
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, false>), grid, block, 0, p->stream,
+                               a0, P, bm, want);
+        else if (p->buf_b)
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, true>), grid, block, 0, p->stream,
+                               a0, P, bm, want);
         else
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false>), dim3(p->total_blocks),
-                               dim3(kNumWavesH * kWave), 0, p->stream, a0, P, bm, (uint8_t)kClsWaveHash);
+            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, false>), grid, block, 0, p->stream,
+                               a0, P, bm, want);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_hash");
     }
@@ -845,7 +866,7 @@ reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_cs
                                  (uint64_t)p->long_rows, (uint64_t)p->long_grid,
                                  (uint64_t)(p->agg.cls[kClsWaveBmpS] > 0), (uint64_t)(p->agg.cls[kClsWaveHash] > 0),
                                  (uint64_t)sizeof(T), (uint64_t)sizeof(IdxT), (uint64_t)sizeof(IdxC),
-                                 (uint64_t)(uintptr_t)p->gvals_ptr, (uint64_t)p->gvals_stride};
+                                 (uint64_t)(uintptr_t)p->gvals_ptr, (uint64_t)p->gvals_stride, (uint64_t)p->buf_b};
     const reap_status_t st =
         run_pass(p, p->g_num, p->g_num_key, key, [&]() { return launch_numeric<T, IdxT, IdxC>(p, a0); });
     if (st == REAP_OK && p->use_graph) {
