@@ -58,7 +58,7 @@ struct StEnt<IdxT, true> {
 };
 
 template <typename IdxT, bool VALS, int ROWS, int CAP>
-struct ChunkStage {
+struct alignas(16) ChunkStage {
     StEnt<IdxT, VALS> ent[CAP];    // first, so that 16-byte entries stay 16-byte aligned
     int32_t rowoff[ROWS + 1];      // entries of row r: [rowoff[r], rowoff[r + 1])
 };
@@ -480,7 +480,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
 
 // LDS of one wavefront of the compact bitmap numeric kernel.
 template <typename IdxT, int NCMAX>
-struct NumBmpLds {
+struct alignas(16) NumBmpLds {
     uint32_t bits[kBmpAlloc];     // circular bitmap (+ a dummy word per lane)
     uint8_t pfx[kBmpAlloc];       // entries of the row before each word (8 bits: rows hold < 256)
     double vals[NCMAX + kWave];   // accumulators by rank (+ a dummy per lane)
