@@ -260,13 +260,27 @@ __device__ __forceinline__ void bmp_clear(uint32_t* bits) {
         *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane_id())) = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Sets the bit of every slot's column.  A lane's entries of one step are
+// consecutive entries of one B row, so neighbouring ones often share a word:
+// their bits are merged in registers and the word is updated once.
 template <int S>
 __device__ __forceinline__ void bmp_or(uint32_t* bits, const int32_t (&c)[S][kLaneEntries],
                                        const int (&pos)[S][kLaneEntries]) {
 #pragma unroll
-    for (int t = 0; t < S; ++t)
+    for (int t = 0; t < S; ++t) {
+        uint32_t m[kLaneEntries];
 #pragma unroll
-        for (int u = 0; u < kLaneEntries; ++u) atomicOr(&bits[pos[t][u]], 1u << (c[t][u] & 31));
+        for (int u = 0; u < kLaneEntries; ++u) m[u] = 1u << (c[t][u] & 31);
+#pragma unroll
+        for (int u = kLaneEntries - 1; u > 0; --u)
+            if (pos[t][u] == pos[t][u - 1]) {
+                m[u - 1] |= m[u];
+                m[u] = 0u;
+            }
+#pragma unroll
+        for (int u = 0; u < kLaneEntries; ++u)
+            if (m[u]) atomicOr(&bits[pos[t][u]], m[u]);
+    }
 }
 
 // Set bits of the whole bitmap, summed over the wavefront.
