@@ -113,6 +113,16 @@ class DeviceCSR:
         return (self.row_ptr.cpu().numpy(), self.col.cpu().numpy(), self.val.cpu().numpy())
 
     def c_struct(self) -> reap_csr_t:
+        # built once per set of tensors (the same operand is passed call after call)
+        key = (id(self.row_ptr), id(self.col), id(self.val), self.rows, self.cols)
+        cached = self.__dict__.get("_cs")
+        if cached is not None and cached[0] == key:
+            return cached[1]
+        s = self._make_struct()
+        self.__dict__["_cs"] = (key, s)
+        return s
+
+    def _make_struct(self) -> reap_csr_t:
         for t in (self.row_ptr, self.col, self.val):
             if not t.is_contiguous():
                 raise ValueError("CSR tensors must be contiguous")

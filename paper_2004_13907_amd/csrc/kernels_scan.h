@@ -21,6 +21,9 @@ struct ScanArgs {
     const WGPart* parts;   // [nparts] statistics of the wavefront symbolic kernel
     Counters* ctr;
     void* c_rp;            // [m + 1] C row pointer (IdxC)
+    Counters* h_ctr;       // the product's counters in pinned host memory (device-mapped), or null
+    const unsigned int* n_long;   // long-row count of the batch ...
+    unsigned int* h_nlong;        // ... and its host copy (written by product 0), or null
 };
 
 // Tile t of product q: tile_start[q] <= blockIdx.x < tile_start[q + 1].
@@ -117,6 +120,11 @@ __global__ void __launch_bounds__(1024) k_scan_spine(ScanArgs s0, const ScanArgs
         ctr->max_nnz = max(ctr->max_nnz, mn);
         ctr->nnz = (unsigned long long)carry;
         c_rp[m] = (IdxC)carry;
+        // the host reads the counters straight from its pinned mirror once
+        // the stream is synchronised (no device-to-host copy is enqueued)
+        if (sa.h_ctr) *sa.h_ctr = *ctr;
+        if (sa.h_nlong && blockIdx.x == 0) *sa.h_nlong = *sa.n_long;
+        __threadfence_system();
     }
 }
 

@@ -130,6 +130,7 @@ struct reap_spgemm_s {
 
     // pinned host memory: counters mirror (+ long-row count) and argument staging
     Counters* h_ctr = nullptr;
+    Counters* h_ctr_dev = nullptr; // the same pinned memory as the device sees it
     size_t h_ctr_cap = 0;          // products
     char* h_stage = nullptr;       // symbolic tables
     char* h_stage_num = nullptr;   // numeric table
@@ -255,12 +256,16 @@ reap_status_t ensure_host(reap_spgemm_s* p, int nprod) {
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
     p->h_ctr = nullptr;
+    p->h_ctr_dev = nullptr;
     p->h_stage = p->h_stage_num = nullptr;
     p->stage_cap = 0;
     const size_t cap = std::max<size_t>((size_t)nprod, 1);
     const size_t ctr_bytes = (cap + 1) * sizeof(Counters);  // the last slot holds the long-row count
     const size_t stage_bytes = cap * (kArgBytes + sizeof(ScanArgs)) + 2 * (cap + 1) * sizeof(int32_t) + 256;
-    if (hipHostMalloc(reinterpret_cast<void**>(&p->h_ctr), ctr_bytes, hipHostMallocDefault) != hipSuccess ||
+    // the counter mirror is written by the scan kernel itself: coherent, device-mapped
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->h_ctr), ctr_bytes, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&p->h_ctr_dev), p->h_ctr, 0) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&p->h_stage), stage_bytes, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&p->h_stage_num), cap * kArgBytes + 256, hipHostMallocDefault) !=
             hipSuccess) {
@@ -506,10 +511,8 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
     }
     debug_step(p, "k_scan");
     ev_record(p, kPhScan, true);
-    // counters of every product, then the long-row count, to the host
-    REAP_HIP(hipMemcpyAsync(p->h_ctr, p->ctr, (size_t)p->nprod * sizeof(Counters), hipMemcpyDeviceToHost, p->stream));
-    REAP_HIP(hipMemcpyAsync(reinterpret_cast<char*>(p->h_ctr) + (size_t)p->h_ctr_cap * sizeof(Counters), p->n_long,
-                            sizeof(unsigned int), hipMemcpyDeviceToHost, p->stream));
+    // the spine kernel has written every product's counters and the long-row
+    // count into the pinned host mirror
     return REAP_OK;
 }
 
@@ -555,6 +558,9 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
         s.parts = p->parts + ps.block_off;
         s.ctr = p->ctr + q;
         s.c_rp = c_row_ptr[q];
+        s.h_ctr = p->h_ctr_dev + q;
+        s.n_long = p->n_long;
+        s.h_nlong = reinterpret_cast<unsigned int*>(p->h_ctr_dev + p->h_ctr_cap);
         // the kernels index the table as an array of this instantiation's type
         std::memcpy(h + (size_t)q * sizeof(a), &a, sizeof(a));
         std::memcpy(h + (size_t)nprod * kArgBytes + (size_t)q * sizeof(ScanArgs), &s, sizeof(s));
