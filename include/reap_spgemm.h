@@ -116,6 +116,12 @@ typedef struct {
  *                        accumulators or transpose scratch, counted from 1)
  *                        fails as if the device were out of memory, so the
  *                        call returns REAP_ERR_OUT_OF_MEMORY; 0 = never.
+ *   scan_onepass_tiles -- batches whose products all have at most this many
+ *                        scan tiles (2048 rows each) build C's row pointer
+ *                        with one kernel launch; larger ones with two (a
+ *                        per-product spine over the tile sums, then the
+ *                        rows).  <= 1024; 0 = default 1024; negative: always
+ *                        two launches.
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -130,7 +136,8 @@ typedef struct {
     int32_t graph;
     int32_t long_workgroups_per_cu;
     int32_t test_fail_alloc;
-    int32_t reserved[5];
+    int32_t scan_onepass_tiles;
+    int32_t reserved[4];
 } reap_options_t;
 
 /*

@@ -67,7 +67,8 @@ class reap_options_t(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("long_workgroups_per_cu", ctypes.c_int32),
         ("test_fail_alloc", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("scan_onepass_tiles", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

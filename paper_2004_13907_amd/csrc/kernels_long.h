@@ -201,6 +201,7 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 
     const int w = threadIdx.x / kWave;
     const int nL = (int)*bm.n_long;
+    if (nL == 0) return;   // the usual case on regular inputs: leave before touching the queue
     for (;;) {
         if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[0], 1u);
         __syncthreads();
@@ -273,6 +274,7 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
         if (threadIdx.x == 0) {
             p.rnnz[i] = (int32_t)nnz;
             p.win[i] = make_int2(lo, (int)span);
+            if (nnz) atomicAdd(&p.tiles[i / kScanTile], (unsigned long long)nnz);
             atomicAdd(&p.ctr->products, (unsigned long long)prods);
             atomicMax(&p.ctr->max_prod, (unsigned)min(prods, (long long)UINT32_MAX));
             atomicMax(&p.ctr->max_nnz, (unsigned)nnz);

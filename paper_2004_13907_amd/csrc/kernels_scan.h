@@ -7,10 +7,6 @@
 
 namespace reap {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;  // rows per tile
-
 // Per-product view of the scan.
 struct ScanArgs {
     const int32_t* rnnz;   // [m] nnz of each row of C
@@ -24,6 +20,7 @@ struct ScanArgs {
     Counters* h_ctr;       // the product's counters in pinned host memory (device-mapped), or null
     const unsigned int* n_long;   // long-row count of the batch ...
     unsigned int* h_nlong;        // ... and its host copy (written by product 0), or null
+    TileStat* h_tiles;     // [ntiles] the product's tile statistics in pinned host memory (one-launch scan)
 };
 
 // Tile t of product q: tile_start[q] <= blockIdx.x < tile_start[q + 1].
@@ -152,13 +149,109 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(ScanArgs s0, const 
     }
 }
 
-// Zeroes the counters (a kernel rather than a memset, so the sequence can be
+// One-launch scan, used when no product has more than kScanOnePassTiles
+// tiles.  The symbolic kernels have already added every row's count into its
+// tile's sum, so tile t of a product learns its offset by summing the sums of
+// tiles 0..t-1 itself (a few loads per thread) and no workgroup waits for
+// another or synchronises with another.  Wavefront 0 of each tile's workgroup
+// folds the statistics of the wavefront workgroups that covered the tile's
+// rows and writes them, with the tile's entry count, to the pinned host
+// mirror; the host adds the tiles up after the pass.  The extra workgroup
+// b == total_tiles copies every product's counters (what the long-row kernel
+// accumulated) and the long-row count to the host mirror and writes
+// row_ptr[0] = 0 of products without rows.
+constexpr int kScanOnePassTiles = 1024;
+
+template <typename IdxC>
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_onepass(ScanArgs s0, const ScanArgs* __restrict__ S, ScanMap sm, int total_tiles) {
+    __shared__ long long s_red[kScanThreads / kWave];
+    const int b = (int)blockIdx.x;
+    if (b == total_tiles) {
+        const int nprod = sm.nprod;
+        constexpr int words = (int)(sizeof(Counters) / 4);
+        for (int x = threadIdx.x; x < nprod * words; x += kScanThreads) {
+            const ScanArgs& sa = S ? S[x / words] : s0;
+            reinterpret_cast<uint32_t*>(sa.h_ctr)[x % words] = reinterpret_cast<const uint32_t*>(sa.ctr)[x % words];
+        }
+        for (int q = threadIdx.x; q < nprod; q += kScanThreads) {
+            const ScanArgs& sa = S ? S[q] : s0;
+            if (sa.m == 0) static_cast<IdxC*>(sa.c_rp)[0] = (IdxC)0;
+        }
+        if (threadIdx.x == 0) *s0.h_nlong = *s0.n_long;
+        return;
+    }
+    ScanArgs sa;
+    int t;
+    scan_tile_of(s0, S, sm, sa, t);
+    const long long* __restrict__ tile_sums = sa.tiles;
+    long long pre = 0;
+    for (int x = threadIdx.x; x < t; x += kScanThreads) pre += tile_sums[x];
+    block_excl_scan_i64<kScanThreads>(pre, s_red, &pre);
+
+    IdxC* __restrict__ c_rp = static_cast<IdxC*>(sa.c_rp);
+    const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    long long sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = (base + j < sa.m) ? sa.rnnz[base + j] : 0;
+        sum += v[j];
+    }
+    long long total;
+    long long run = pre + block_excl_scan_i64<kScanThreads>(sum, s_red, &total);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < sa.m) c_rp[base + j] = (IdxC)run;
+        run += v[j];
+    }
+    if (t == sa.ntiles - 1 && threadIdx.x == 0) c_rp[sa.m] = (IdxC)(pre + total);
+
+    if (threadIdx.x < kWave) {
+        constexpr int per_tile = kScanTile / kRowsPerBlock;
+        const int x0 = t * per_tile, x1 = min(sa.nparts, x0 + per_tile);
+        unsigned long long prod = 0;
+        unsigned int cls[kNumClasses] = {0, 0, 0, 0, 0};
+        unsigned int mp = 0, mn = 0;
+        for (int x = x0 + (int)threadIdx.x; x < x1; x += kWave) {
+            const WGPart& q = sa.parts[x];
+            prod += q.products;
+#pragma unroll
+            for (int c = 0; c < kNumClasses; ++c) cls[c] += q.cls[c];
+            mp = max(mp, q.max_prod);
+            mn = max(mn, q.max_nnz);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            prod += __shfl_xor(prod, o, kWave);
+#pragma unroll
+            for (int c = 0; c < kNumClasses; ++c) cls[c] += __shfl_xor(cls[c], o, kWave);
+            mp = max(mp, __shfl_xor(mp, o, kWave));
+            mn = max(mn, __shfl_xor(mn, o, kWave));
+        }
+        // lanes write the record's words in parallel
+        uint32_t w[sizeof(TileStat) / 4] = {(uint32_t)total, (uint32_t)((unsigned long long)total >> 32),
+                                            (uint32_t)prod, (uint32_t)(prod >> 32),
+                                            cls[0], cls[1], cls[2], cls[3], cls[4], mp, mn, 0u};
+        static_assert(sizeof(TileStat) == 48 && kNumClasses == 5, "tile record layout");
+        const int l = (int)threadIdx.x;
+        uint32_t mine = 0;
+#pragma unroll
+        for (int x = 0; x < 12; ++x) mine = (l == x) ? w[x] : mine;
+        if (l < 12) reinterpret_cast<uint32_t*>(sa.h_tiles + t)[l] = mine;
+    }
+}
+
+// Zeroes the counters, the long-row count and queue words, and the scan
+// tiles' sums (a kernel rather than a memset, so the sequence can be
 // captured in a graph).
-__global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long) {  // n_long[0..2]
+__global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long, long long* tiles, int ntiles) {
     uint32_t* p = reinterpret_cast<uint32_t*>(ctr);
     const int64_t words = (int64_t)nprod * (int64_t)(sizeof(Counters) / 4);
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < words; x += (int64_t)gridDim.x * blockDim.x)
-        p[x] = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t x0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t x = x0; x < words; x += stride) p[x] = 0u;
+    for (int64_t x = x0; x < ntiles; x += stride) tiles[x] = 0;
     if (blockIdx.x == 0 && threadIdx.x < 3) n_long[threadIdx.x] = 0u;  // count and the two queue counters
 }
 

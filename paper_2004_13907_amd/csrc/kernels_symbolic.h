@@ -21,6 +21,7 @@ struct SymArgs {
     gptr<int2> win;            // [m] {lo, words} bitmap window of wavefront rows; {lo, span} of long rows
     gptr<Counters> ctr;        // this product's counters
     gptr<WGPart> parts;        // per-workgroup statistics of the wavefront symbolic kernel
+    gptr<unsigned long long> tiles;  // [ceil(m / kScanTile)] sum of rnnz over each scan tile (zeroed before)
     Thresholds th;
 };
 

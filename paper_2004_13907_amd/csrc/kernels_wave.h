@@ -374,12 +374,14 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
 // numeric kernels hold go to the long-row list.
 // TAB: arguments from the batch table (else the by-value argument of a single product).
 template <typename IdxT, bool TAB, bool BUF>
-__global__ void __launch_bounds__(kWaveKernelWaves * 64)
+__global__ void __launch_bounds__(kWaveKernelWaves * 64) __attribute__((amdgpu_waves_per_eu(6)))
 k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     constexpr int W = kWaveKernelWaves;
     __shared__ __align__(16) uint32_t s_bits[W][kBmpAlloc];
     __shared__ __align__(16) ChunkStage<IdxT, false, kRowsPerWave, kStageCap> s_stage[W];
     __shared__ WGPart s_part[W];
+    __shared__ int s_nnz[W];
+    static_assert(W == 4, "tile sum adds four wavefronts");
 
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -399,6 +401,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     uint8_t my_cls = 0;
     int my_nnz = 0;
     int2 my_win = make_int2(0, 0);
+    int wave_nnz = 0;   // a wavefront row has at most 1024 entries: no overflow
 
     const int nrows = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - row0));
     const bool staged = nrows > 0 && stage_chunk<float, IdxT, false>(st, row0, nrows, p.a_rp, p.a_col,
@@ -450,6 +453,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
             my_nnz = nnz;
             my_win = win;
         }
+        wave_nnz += cls == kClsGroup ? 0 : __builtin_amdgcn_readfirstlane(nnz);   // the wavefront's share of its scan tile's sum
 #pragma unroll
         for (int cl = 0; cl < kNumClasses; ++cl) cnt[cl] += (cls == cl) ? 1u : 0u;
         if (cls == kClsGroup) group_flags |= 1u << r;
@@ -473,6 +477,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     }
 
     if (lane == 0) {
+        s_nnz[w] = wave_nnz;
         WGPart& s = s_part[w];
         s.products = prod_acc;
         for (int cl = 0; cl < kNumClasses; ++cl) s.cls[cl] = cnt[cl];
@@ -489,6 +494,8 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
             t.max_nnz = max(t.max_nnz, s_part[x].max_nnz);
         }
         p.parts[blk] = t;
+        const int tn = s_nnz[0] + s_nnz[1] + s_nnz[2] + s_nnz[3];
+        if (tn) atomicAdd(&p.tiles[(int64_t)blk * kRowsPerBlock / kScanTile], (unsigned long long)tn);
     }
 }
 

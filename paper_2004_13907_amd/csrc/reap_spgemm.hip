@@ -101,6 +101,7 @@ struct reap_spgemm_s {
     bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
     int long_wg_per_cu = 2;   // workgroups per CU walking the long-row list
     int fail_alloc_at = 0;    // test hook: the n-th device allocation of the plan fails (0 = never)
+    int scan_onepass = kScanOnePassTiles;  // most tiles per product for the one-launch scan
     int alloc_count = 0;      // device allocations attempted by the plan
 
     Workspace ws;      // counters, per-row arrays, tables
@@ -131,6 +132,10 @@ struct reap_spgemm_s {
     // pinned host memory: counters mirror (+ long-row count) and argument staging
     Counters* h_ctr = nullptr;
     Counters* h_ctr_dev = nullptr; // the same pinned memory as the device sees it
+    TileStat* h_tiles = nullptr;   // per-tile statistics of the one-launch scan (pinned, device-mapped)
+    TileStat* h_tiles_dev = nullptr;
+    size_t h_tiles_cap = 0;        // tiles
+    bool scan_onepass_used = false;
     size_t h_ctr_cap = 0;          // products
     char* h_stage = nullptr;       // symbolic tables
     char* h_stage_num = nullptr;   // numeric table
@@ -146,6 +151,7 @@ struct reap_spgemm_s {
     reap_index_t in_idx = REAP_I32;
     int64_t total_rows = 0;
     int32_t total_blocks = 0, total_tiles = 0;
+    int32_t max_prod_tiles = 0;     // most scan tiles of one product in the batch
     unsigned int long_rows = 0;
     int long_grid = 1;
     int64_t gvals_stride = 0;
@@ -244,6 +250,27 @@ WsLayout ws_layout(int64_t R, int32_t Bk, int32_t Tl, int64_t Q) {
     L.o_sc = carve((size_t)Q * sizeof(ScanArgs));
     L.total = off;
     return L;
+}
+
+// Pinned, device-mapped records of `ntiles` scan tiles for the one-launch scan.
+reap_status_t ensure_host_tiles(reap_spgemm_s* p, size_t ntiles) {
+    if (ntiles <= p->h_tiles_cap && p->h_tiles) return REAP_OK;
+    (void)hipStreamSynchronize(p->stream);
+    release_graphs(p);  // captured scans write the old records
+    if (p->h_tiles) (void)hipHostFree(p->h_tiles);
+    p->h_tiles = p->h_tiles_dev = nullptr;
+    p->h_tiles_cap = 0;
+    const size_t cap = std::max<size_t>(ntiles, kScanOnePassTiles);
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->h_tiles), cap * sizeof(TileStat),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&p->h_tiles_dev), p->h_tiles, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->h_tiles) (void)hipHostFree(p->h_tiles);
+        p->h_tiles = p->h_tiles_dev = nullptr;
+        return REAP_ERR_OUT_OF_MEMORY;
+    }
+    p->h_tiles_cap = cap;
+    return REAP_OK;
 }
 
 // Pinned staging and counter mirror for `nprod` products.
@@ -437,6 +464,26 @@ reap_status_t run_pass(reap_spgemm_s* p, hipGraphExec_t& exec, std::vector<uint6
 }
 
 // ---------------------------------------------------------------------------
+// C's row pointer from the tile sums: one launch when every product has at
+// most p->scan_onepass tiles (and the tile records fit the host mirror), else
+// the per-product spine and the row kernel.
+template <typename IdxC>
+reap_status_t launch_row_ptr_scan(reap_spgemm_s* p, const ScanArgs& s0, const ScanArgs* S, ScanMap sm) {
+    if (p->scan_onepass_used) {
+        hipLaunchKernelGGL(k_scan_onepass<IdxC>, dim3(p->total_tiles + 1), dim3(kScanThreads), 0, p->stream, s0, S,
+                           sm, p->total_tiles);
+        REAP_LAUNCH_CHECK();
+        return REAP_OK;
+    }
+    hipLaunchKernelGGL(k_scan_spine<IdxC>, dim3(p->nprod), dim3(1024), 0, p->stream, s0, S);
+    REAP_LAUNCH_CHECK();
+    if (p->total_tiles > 0) {
+        hipLaunchKernelGGL(k_scan_apply<IdxC>, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S, sm);
+        REAP_LAUNCH_CHECK();
+    }
+    return REAP_OK;
+}
+
 // Symbolic pass of the current batch (tables already in the staging buffer).
 
 template <typename IdxT>
@@ -461,8 +508,10 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
         h += (size_t)(p->nprod + 1) * 4;
         REAP_HIP(hipMemcpyAsync(p->tile_start, h, (size_t)(p->nprod + 1) * 4, hipMemcpyHostToDevice, p->stream));
     }
-    const int zb = (int)std::min<int64_t>(1024, ((int64_t)p->nprod * (int64_t)(sizeof(Counters) / 4) + 255) / 256);
-    hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, p->nprod, p->n_long);
+    const int64_t zw = std::max<int64_t>((int64_t)p->nprod * (int64_t)(sizeof(Counters) / 4), p->total_tiles);
+    const int zb = (int)std::min<int64_t>(1024, (zw + 255) / 256);
+    hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, p->nprod, p->n_long,
+                       p->tiles, p->total_tiles);
     REAP_LAUNCH_CHECK();
 
     ev_record(p, kPhSymbolic, false);
@@ -487,28 +536,10 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
     }
     ev_record(p, kPhSymbolic, true);
     ev_record(p, kPhScan, false);
-    if (p->total_tiles > 0) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S, sm);
-        REAP_LAUNCH_CHECK();
-        debug_step(p, "k_scan_tiles");
-    }
-    if (p->cidx == REAP_I32) {
-        hipLaunchKernelGGL(k_scan_spine<int32_t>, dim3(p->nprod), dim3(1024), 0, p->stream, s0, S);
-        REAP_LAUNCH_CHECK();
-        if (p->total_tiles > 0) {
-            hipLaunchKernelGGL(k_scan_apply<int32_t>, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S,
-                               sm);
-            REAP_LAUNCH_CHECK();
-        }
-    } else {
-        hipLaunchKernelGGL(k_scan_spine<int64_t>, dim3(p->nprod), dim3(1024), 0, p->stream, s0, S);
-        REAP_LAUNCH_CHECK();
-        if (p->total_tiles > 0) {
-            hipLaunchKernelGGL(k_scan_apply<int64_t>, dim3(p->total_tiles), dim3(kScanThreads), 0, p->stream, s0, S,
-                               sm);
-            REAP_LAUNCH_CHECK();
-        }
-    }
+    // the symbolic kernels have summed every scan tile
+    reap_status_t st = p->cidx == REAP_I32 ? launch_row_ptr_scan<int32_t>(p, s0, S, sm)
+                                           : launch_row_ptr_scan<int64_t>(p, s0, S, sm);
+    if (st != REAP_OK) return st;
     debug_step(p, "k_scan");
     ev_record(p, kPhScan, true);
     // the spine kernel has written every product's counters and the long-row
@@ -548,6 +579,7 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
         a.win = to_gptr(p->win + ps.row_off);
         a.ctr = to_gptr(p->ctr + q);
         a.parts = to_gptr(p->parts + ps.block_off);
+        a.tiles = to_gptr(reinterpret_cast<unsigned long long*>(p->tiles + ps.tile_off));
         a.th = p->th;
         ScanArgs s{};
         s.rnnz = p->rnnz + ps.row_off;
@@ -561,6 +593,7 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
         s.h_ctr = p->h_ctr_dev + q;
         s.n_long = p->n_long;
         s.h_nlong = reinterpret_cast<unsigned int*>(p->h_ctr_dev + p->h_ctr_cap);
+        s.h_tiles = p->scan_onepass_used ? p->h_tiles_dev + ps.tile_off : nullptr;
         // the kernels index the table as an array of this instantiation's type
         std::memcpy(h + (size_t)q * sizeof(a), &a, sizeof(a));
         std::memcpy(h + (size_t)nprod * kArgBytes + (size_t)q * sizeof(ScanArgs), &s, sizeof(s));
@@ -580,7 +613,8 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
 
     if (p->validate) {
         const int zb = (int)std::min<int64_t>(1024, ((int64_t)nprod * (int64_t)(sizeof(Counters) / 4) + 255) / 256);
-        hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, nprod, p->n_long);
+        hipLaunchKernelGGL(k_zero_counters, dim3(std::max(zb, 1)), dim3(256), 0, p->stream, p->ctr, nprod, p->n_long,
+                           p->tiles, 0);
         REAP_LAUNCH_CHECK();
         reap_status_t st;
         for (int q = 0; q < nprod; ++q) {
@@ -596,7 +630,8 @@ reap_status_t symbolic_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_c
     if (!p->use_graph || p->eager) return launch_symbolic<IdxT>(p, a0, s0);
     std::vector<uint64_t> key = {p->ws_generation, (uint64_t)nprod, (uint64_t)p->total_blocks,
                                  (uint64_t)p->total_tiles, (uint64_t)p->total_rows, (uint64_t)p->cidx,
-                                 (uint64_t)sizeof(IdxT), (uint64_t)p->buf_b};
+                                 (uint64_t)sizeof(IdxT), (uint64_t)p->buf_b,
+                                 (uint64_t)p->scan_onepass_used};
     return run_pass(p, p->g_sym, p->g_sym_key, key, [&]() { return launch_symbolic<IdxT>(p, a0, s0); });
 }
 
@@ -666,7 +701,7 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     p->prods.assign((size_t)count, ProdState{});
     p->in_idx = in_idx;
     int64_t ro = 0;
-    int32_t bo = 0, to = 0;
+    int32_t bo = 0, to = 0, mt = 0;
     for (int64_t q = 0; q < count; ++q) {
         ProdState& ps = p->prods[(size_t)q];
         ps.m = A[q].rows;
@@ -682,6 +717,14 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
         ro += ps.m;
         bo += ps.blocks;
         to += ps.tiles;
+        mt = std::max(mt, ps.tiles);
+    }
+    p->max_prod_tiles = mt;
+    p->scan_onepass_used = false;
+    if (mt <= p->scan_onepass) {
+        // the allocation-free call uses the records made at create, if they suffice
+        if (!noalloc && (st = ensure_host_tiles(p, (size_t)to)) != REAP_OK) return st;
+        p->scan_onepass_used = (size_t)to <= p->h_tiles_cap;
     }
     p->total_rows = ro;
     p->total_blocks = bo;
@@ -703,8 +746,19 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     unsigned int max_group_nnz = 0;
     bool overflow = false;
     for (int q = 0; q < p->nprod; ++q) {
-        const Counters& h = p->h_ctr[q];
+        Counters h = p->h_ctr[q];
         ProdState& ps = p->prods[(size_t)q];
+        if (p->scan_onepass_used) {
+            // the one-launch scan left the wavefront rows' statistics per tile
+            for (int t = 0; t < ps.tiles; ++t) {
+                const TileStat& ts = p->h_tiles[ps.tile_off + t];
+                h.nnz += ts.nnz;
+                h.products += ts.products;
+                for (int c = 0; c < kNumClasses; ++c) h.cls[c] += ts.cls[c];
+                h.max_prod = std::max(h.max_prod, ts.max_prod);
+                h.max_nnz = std::max(h.max_nnz, ts.max_nnz);
+            }
+        }
         ps.c_nnz = (int64_t)h.nnz;
         ps.products = (int64_t)h.products;
         c_nnz[q] = ps.c_nnz;
@@ -1082,6 +1136,7 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     p->th.group_lds_values = clampi(o.group_lds_values, kLongMinVals, kLongVals, kLongVals);
     p->long_wg_per_cu = clampi(o.long_workgroups_per_cu, 1, 8, 2);
     p->fail_alloc_at = std::max(0, o.test_fail_alloc);
+    p->scan_onepass = clampi(o.scan_onepass_tiles, 0, kScanOnePassTiles, kScanOnePassTiles);
 
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -1096,7 +1151,10 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
         return REAP_ERR_HIP;
     }
     p->prods.reserve(1);  // one product's record: the allocation-free call never grows it
-    if (ensure_host(p, 1) != REAP_OK) {
+    if (ensure_host(p, 1) != REAP_OK || ensure_host_tiles(p, kScanOnePassTiles) != REAP_OK) {
+        if (p->h_ctr) (void)hipHostFree(p->h_ctr);
+        if (p->h_stage) (void)hipHostFree(p->h_stage);
+        if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
         (void)hipEventDestroy(p->ev_num_upload);
         delete p;
         return REAP_ERR_OUT_OF_MEMORY;
@@ -1118,6 +1176,7 @@ reap_status_t reap_spgemm_destroy(reap_spgemm_t p) {
     if (p->gvals.base) (void)hipFree(p->gvals.base);
     if (p->tws.base) (void)hipFree(p->tws.base);
     if (p->h_ctr) (void)hipHostFree(p->h_ctr);
+    if (p->h_tiles) (void)hipHostFree(p->h_tiles);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->h_stage_num) (void)hipHostFree(p->h_stage_num);
     if (p->ev_num_upload) (void)hipEventDestroy(p->ev_num_upload);

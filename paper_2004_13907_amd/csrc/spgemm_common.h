@@ -68,10 +68,30 @@ struct Counters {
     unsigned int pad[4];
 };
 
+// Statistics of one scan tile, written by the one-launch scan into pinned
+// host memory; the host adds the tiles of each product to its counters.
+struct TileStat {
+    unsigned long long nnz;        // entries of C in the tile's rows
+    unsigned long long products;   // partial products of the tile's wavefront rows
+    unsigned int cls[kNumClasses]; // rows per class
+    unsigned int max_prod;
+    unsigned int max_nnz;
+    unsigned int pad;
+};
+
 // Rows handled by one workgroup of the wavefront kernels (4 wavefronts of
 // kRowsPerWave rows); the batch's block table is built for this many rows.
 constexpr int kWaveKernelWaves = 4;
 constexpr int kRowsPerBlock = kWaveKernelWaves * kRowsPerWave;
+
+// Scan of the row counts into C's row pointer: tiles of kScanTile rows.  The
+// symbolic kernels add each row's count into its tile's sum as they go, so a
+// workgroup of a wavefront kernel (whose rows never straddle two tiles) adds
+// once per launch.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // rows per tile
+static_assert(kScanTile % kRowsPerBlock == 0, "a wavefront workgroup's rows lie in one scan tile");
 
 // Several independent products in one launch.  Workgroup b of a wavefront
 // kernel serves product q with blk_start[q] <= b < blk_start[q + 1]; its

@@ -141,6 +141,7 @@ PATHS = {
     "hash_tiny_wave": {"wave_max_span": 40, "wave_hash_products": 48, "wave_max_products": 200},
     "long_chunks": {"wave_max_products": -1, "group_lds_values": 256},
     "long_chunks_segments": {"wave_max_products": 8, "group_lds_span": 320, "group_lds_values": 256},
+    "scan_two_launch": {"scan_onepass_tiles": -1},
 }
 
 # What each forced path must show in the plan's statistics (rows per class,
@@ -157,6 +158,7 @@ PATH_EXPECT = {
     "hash_tiny_wave": lambda st: st["group"] > 0,
     "long_chunks": lambda st: _all_long(st),
     "long_chunks_segments": lambda st: st["group"] > 0,
+    "scan_two_launch": lambda st: True,
 }
 # paths whose effect must show on the light irregular pairs (seed 2 and the
 # sparse pair: rows of a few dozen to a few hundred products; a hash row
@@ -577,6 +579,65 @@ def test_numeric_past_int32_offsets(reap):
     local_rp = np.zeros(rows.size + 1, dtype=np.int64)
     np.cumsum(rp[rows + 1] - rp[rows], out=local_rp[1:])
     compare_rows(ref, np.arange(rows.size), local_rp, gcol, gval, np.float64, "rows past 2^31")
+
+
+def test_scan_many_tiles(reap):
+    """A product of 2^21 + 4099 rows (1027 scan tiles of 2048 rows): past the
+    one-launch scan's limit, so the row pointer comes from the per-product
+    spine; every entry against the oracle.  A selects one scaled row of B per
+    row of C (row i of C is a_i times row sel(i) of B)."""
+    m = (1 << 21) + 4099
+    rng = np.random.default_rng(41)
+    B = synth.uniform_rows(3000, 4000, 5, seed=42).astype(np.float64)
+    sel = rng.integers(0, B.rows, size=m).astype(np.int32)
+    A = synth.CSR(m, B.rows, np.arange(m + 1, dtype=np.int32), sel, rng.uniform(-2, 2, size=m))
+    say("scan past the one-launch tile limit: m", m)
+    dA = reap.DeviceCSR.from_host(A, dtype=torch.float64)
+    dB = reap.DeviceCSR.from_host(B, dtype=torch.float64)
+    ref = oracle.spgemm(A, B, threads=_threads())
+    results = {}
+    for name, kw in (("auto", {}), ("two launches", {"scan_onepass_tiles": -1})):
+        with reap.Plan(torch.float64, **kw) as plan:
+            rp_d, nnz, prods = plan.symbolic(dA, dB)
+            col_d, val_d = plan.numeric(dA, dB, rp_d)
+            torch.cuda.synchronize()
+            results[name] = plan.bin_stats()
+        assert nnz == ref.nnz and prods == ref.total_products
+        compare_full(ref, rp_d.cpu().numpy(), col_d.cpu().numpy(), val_d.cpu().numpy(), np.float64,
+                     "many tiles, " + name)
+    assert results["auto"] == results["two launches"]
+
+
+def test_scan_paths_same_statistics(reap):
+    """The one-launch scan folds the symbolic pass's statistics per tile with
+    atomics, the two-launch scan per product in one workgroup: the plan's
+    statistics and row pointer must not depend on which ran (stencil 64^3 and
+    R-MAT 14 A*A^T, one batch holding both)."""
+    S = synth.stencil27(64).astype(np.float64)
+    R = synth.rmat(14).astype(np.float64)
+    pairs = [(S, S), (R, synth.transpose(R))]
+    say("scan paths: statistics and row pointers agree")
+    dev = [(reap.DeviceCSR.from_host(a, dtype=torch.float64), reap.DeviceCSR.from_host(b, dtype=torch.float64))
+           for a, b in pairs]
+    seen = []
+    for kw in ({}, {"scan_onepass_tiles": -1}):
+        single = []
+        for dA, dB in dev:
+            with reap.Plan(torch.float64, **kw) as plan:
+                rp_d, nnz, prods = plan.symbolic(dA, dB)
+                torch.cuda.synchronize()
+                single.append((rp_d.cpu().numpy(), nnz, prods, plan.bin_stats()))
+        with reap.Batch(torch.float64, **kw) as b:
+            bn = b.symbolic([d[0] for d in dev], [d[1] for d in dev])
+            b.synchronize()
+        assert bn == [x[1] for x in single]
+        seen.append(single)
+    for (rp1, n1, p1, st1), (rp2, n2, p2, st2) in zip(*seen):
+        assert np.array_equal(rp1, rp2) and n1 == n2 and p1 == p2 and st1 == st2
+    for (A, B), (rp, nnz, prods, st) in zip(pairs, seen[0]):
+        pat = oracle.spgemm(A, B, threads=_threads(), with_values=False)
+        assert np.array_equal(rp, pat.row_ptr) and prods == pat.total_products
+        assert st["max_row_products"] == int(pat.products.max())
 
 
 # --- full-size skewed product (last: the largest case) ----------------------------
