@@ -253,11 +253,19 @@ __device__ __forceinline__ void slot_positions(const int32_t (&c)[S][kLaneEntrie
     }
 }
 
-// Clears the circular bitmap: four 16-byte stores per lane, lanes side by side.
-__device__ __forceinline__ void bmp_clear(uint32_t* bits) {
-#pragma unroll
-    for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j)
-        *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane_id())) = make_uint4(0u, 0u, 0u, 0u);
+// Position of quad qd (words 4qd .. 4qd+3 of the circular order) in LDS: the
+// word swizzle moves whole quads (it flips word bits 2-3, i.e. quad bits 0-1).
+__device__ __forceinline__ int bmp_quad_pos(int qd) {
+    qd &= kBmpMask >> 2;
+    return qd ^ ((qd >> 5) & 3);
+}
+
+// Clears the quads holding window words [w0, w0 + nw) (nw <= kBmpMaxWords):
+// one 16-byte store per quad, consecutive quads on consecutive lanes.
+__device__ __forceinline__ void bmp_clear(uint32_t* bits, int w0, int nw) {
+    const int qa = w0 >> 2, nq = ((w0 + nw - 1) >> 2) - qa + 1;
+    for (int x = lane_id(); x < nq; x += kWave)
+        *reinterpret_cast<uint4*>(bits + 4 * bmp_quad_pos(qa + x)) = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Sets the bit of every slot's column.  A lane's entries of one step are
@@ -283,12 +291,12 @@ __device__ __forceinline__ void bmp_or(uint32_t* bits, const int32_t (&c)[S][kLa
     }
 }
 
-// Set bits of the whole bitmap, summed over the wavefront.
-__device__ __forceinline__ int bmp_count(const uint32_t* bits) {
+// Set bits of the window's quads, summed over the wavefront.
+__device__ __forceinline__ int bmp_count(const uint32_t* bits, int w0, int nw) {
+    const int qa = w0 >> 2, nq = ((w0 + nw - 1) >> 2) - qa + 1;
     int pc = 0;
-#pragma unroll
-    for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j) {
-        const uint4 q = *reinterpret_cast<const uint4*>(bits + 4 * (j * kWave + lane_id()));
+    for (int x = lane_id(); x < nq; x += kWave) {
+        const uint4 q = *reinterpret_cast<const uint4*>(bits + 4 * bmp_quad_pos(qa + x));
         pc += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
     }
     return dpp_reduce_sum(pc);
@@ -323,11 +331,11 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
     if (nw <= kBmpMaxWords && (int64_t)cmax - (int64_t)cmin + 1 <= (int64_t)th.wave_max_span) {
         int pos[S][kLaneEntries];
         slot_positions<S>(c, rem, pos);
-        bmp_clear(bits);
+        bmp_clear(bits, (int)(cmin >> 5), nw);
         wave_sync();
         bmp_or<S>(bits, c, pos);
         wave_sync();
-        nnz = bmp_count(bits);
+        nnz = bmp_count(bits, (int)(cmin >> 5), nw);
         win = make_int2((int)cmin, nw);
         cls = nnz <= th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
     } else if (P <= th.wave_hash_products) {
@@ -522,26 +530,28 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     row_loads<S, T, IdxT, true, BUF>(ent, nA, rg, br, c, v, rem, a);
     const int2 wn = p.win[i];
     const int lo_w = uniform_i32(wn.x) >> 5;
+    const int nw = uniform_i32(wn.y);
     const int64_t cb = uniform((int64_t)p.c_rp[i]);
     const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
-    bmp_clear(sh.bits);
+    // from the 16-aligned word where the prefix scan below starts
+    bmp_clear(sh.bits, lo_w & ~15, nw + (lo_w & 15));
     for (int x = lane; x < nc; x += kWave) sh.vals[x] = 0.0;
     int pos[S][kLaneEntries];
     slot_positions<S>(c, rem, pos);
     wave_sync();
     bmp_or<S>(sh.bits, c, pos);
     wave_sync();
-    // prefix counts in window order, in four rounds of 256 words: in round j
-    // lane l takes word quad s0/4 + 64 j + l (s0 the row's first word
-    // rounded down to 16), so that the lanes' 16-byte reads and 4-byte writes
-    // are side by side in LDS; a wavefront scan gives each quad its prefix.
+    // prefix counts in window order, in rounds of 256 words over the window:
+    // in round j lane l takes word quad s0/4 + 64 j + l (s0 the row's first
+    // word rounded down to 16), so that the lanes' 16-byte reads and 4-byte
+    // writes are side by side in LDS; a wavefront scan gives each quad its
+    // prefix.
     {
         const int q0 = ((lo_w & kBmpMask) & ~15) >> 2;   // first quad of the window
+        const int rounds = ((lo_w & 15) + nw + 4 * kWave - 1) / (4 * kWave);
         int carry = 0;
-#pragma unroll
-        for (int j = 0; j < kWaveBitsWords / (4 * kWave); ++j) {
-            const int qd = (q0 + j * kWave + lane) & (kBmpMask >> 2);   // quad in word order
-            const int qp = qd ^ ((qd >> 5) & 3);                        // its position (see bmp_pos)
+        for (int j = 0; j < rounds; ++j) {
+            const int qp = bmp_quad_pos(q0 + j * kWave + lane);
             const uint4 qv = *reinterpret_cast<const uint4*>(sh.bits + 4 * qp);
             const int c0 = __popc(qv.x), c1 = __popc(qv.y), c2 = __popc(qv.z), c3 = __popc(qv.w);
             const int tot = c0 + c1 + c2 + c3;
