@@ -1,11 +1,25 @@
 // Long rows: rows of A with more than 64 entries or more partial products than
 // a wavefront row holds (the paper splits such rows into fixed-size pieces so
 // that no processing element stalls on one row; here a whole workgroup takes
-// the row).  Both passes walk the row's products once per column segment: a
-// segment is a window of up to kLongSegWords * 32 columns whose bitmap lives in
-// LDS.  The symbolic pass counts set bits; the numeric pass also prefix-counts
-// the bitmap words, so that the rank of a column (its position in the sorted
-// row) is one LDS read and a popcount, and adds each product into that slot.
+// the row and cuts its products into equal pieces for its wavefronts).  Both
+// passes walk the row's products once per column segment: a segment is a
+// window of up to kLongSegWords * 32 columns whose bitmap lives in LDS.  The
+// symbolic pass counts set bits; the numeric pass also prefix-counts the
+// bitmap words, so that the rank of a column (its position in the sorted row)
+// is one LDS read and a popcount, and adds each product into that slot.
+//
+// Flattened walks.  The products of a row form one index space: A entry e
+// (thread e of the workgroup holds it) covers the products
+// [pre[e], pre[e + 1]), pre being the exclusive prefix sum of the lengths of
+// the B rows the entries name.  Each wavefront takes steps of 64 * kFlatU
+// consecutive products and each lane kFlatU consecutive ones of a step; a
+// lane finds the entry of its first product by a binary search over pre in
+// LDS and moves to the next entry when its run crosses one.  Every wavefront
+// of the workgroup thus gets the same share of the row whatever the lengths
+// of its B rows (a row of A·Aᵀ on a power-law matrix typically has a dozen
+// entries, some naming B rows of tens of thousands of entries).  Rows with
+// more entries than the workgroup has threads are taken in blocks of that
+// many entries.
 //
 // Rows are taken from the batch's long-row list of (product, row) pairs
 // through a device counter (each workgroup takes the next unprocessed entry
@@ -21,169 +35,167 @@ namespace reap {
 
 constexpr int kLongThreads = 512;       // symbolic pass
 constexpr int kLongWaves = kLongThreads / kWave;
-constexpr int kLongNumThreads = 1024;   // numeric pass (one workgroup per CU: its LDS is ~150 KB)
+constexpr int kLongNumThreads = 1024;   // numeric pass (one workgroup per CU: its LDS is ~156 KB)
 constexpr int kLongNumWaves = kLongNumThreads / kWave;
 constexpr int kLongSegWords = 8192;     // 262144 columns per window segment
 constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS
 constexpr int kLongMinVals = 256;       // smallest rank chunk accepted
 constexpr int kLongMaxChunks = kLongSegWords * 32 / kLongMinVals;
+constexpr int kFlatU = 4;               // consecutive products per lane and step of a flattened walk
 constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a B row read by a long row is not in column order
 
-// Per-wavefront table of one chunk of (at most 64) A entries.
-template <typename IdxT>
-struct LongChunk {
-    IdxT b0[kWave];       // first B entry of the named B row
-    int32_t len[kWave];   // its length when shorter than 64, else 0
-    double a[kWave];      // the A value
+// One block of (at most NT) A entries of a long row, published for a
+// flattened walk: entry e covers the block's products [pre[e], pre[e + 1]),
+// product p of it reads B entry qs[e] + (p - pre[e]) and is scaled by a[e].
+template <int NT, bool VALS>
+struct FlatStage {
+    int64_t pre[NT + 1];
+    int64_t qs[NT];
+    double a[VALS ? NT : 1];
 };
 
-// Calls fn(col, v) once for every partial product of the A row [rs, rs + nA)
-// that this wavefront owns, v = a_ik * b_kj in FP64 (0 when !VALS).
-// Wavefront w takes the chunks of 64 entries starting at w*64,
-// (w + nwaves)*64, ...  Entries whose B row has 64 or more entries are walked
-// by the whole wavefront, 256 consecutive B entries per step (four loads of
-// column and value in flight per lane before any is used).  The other
-// entries of the chunk are taken in groups of G lanes (G the smallest power
-// of two not below the chunk's longest such B row): 64/G entries per step,
-// lane `off` of a group reads B entry b0 + off.  CHECK sets *unsorted when a
-// B row is not in ascending column order.
-template <typename IdxT, typename T, bool VALS, bool CHECK = false, typename Fn>
-__device__ __forceinline__ void long_row_products(IdxT rs, int64_t nA, const int32_t* __restrict__ a_col,
-                                                  const T* __restrict__ a_val, const IdxT* __restrict__ b_rp,
-                                                  const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
-                                                  int wave, int nwaves, LongChunk<IdxT>& tb, Fn&& fn,
-                                                  bool* unsorted = nullptr) {
-    constexpr int U = 4;
-    const int lane = lane_id();
-    for (int64_t ch = (int64_t)wave * kWave; ch < nA; ch += (int64_t)nwaves * kWave) {
-        const int cnt = (int)min((int64_t)kWave, nA - ch);
-        IdxT b0 = 0;
-        int64_t len = 0;
-        double a = 0.0;
-        if (lane < cnt) {
-            const int k = a_col[rs + ch + lane];
-            const IdxT x0 = b_rp[k];
-            const IdxT x1 = b_rp[k + 1];
-            b0 = x0;
-            len = (int64_t)x1 - (int64_t)x0;
-            if (VALS) a = (double)a_val[rs + ch + lane];
-        }
-        const bool lng = len >= kWave;
-        const int slen = lng ? 0 : (int)len;
-        const int maxs = wave_max_i32(slen);
-        if (maxs > 0) {
-            tb.b0[lane] = b0;
-            tb.len[lane] = slen;
-            if (VALS) tb.a[lane] = a;
-            wave_sync();
-            const int logG = maxs <= 1 ? 0 : 32 - __clz(maxs - 1);
-            const int g = lane >> logG;
-            const int off = lane & ((1 << logG) - 1);
-            const int per = kWave >> logG;
-            // two steps per trip: the loads of both are issued before either is used
-            for (int e0 = 0; e0 < cnt; e0 += 2 * per) {
-                int c[2];
-                T bv[2];
-                bool on[2];
-                int ei[2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int e = e0 + u * per + g;
-                    ei[u] = e;
-                    on[u] = e < cnt && off < tb.len[e];
-                    c[u] = -1;
-                    bv[u] = T(0);
-                    if (on[u]) {
-                        const IdxT q = tb.b0[e] + (IdxT)off;
-                        c[u] = b_col[q];
-                        if (VALS) bv[u] = b_val[q];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    if (CHECK) {
-                        // lane - 1 holds the previous entry of the same B row when off > 0
-                        const int prev = __shfl_up(c[u], 1, kWave);
-                        if (on[u] && off > 0 && prev > c[u]) *unsorted = true;
-                    }
-                    if (on[u]) fn(c[u], VALS ? tb.a[ei[u]] * (double)bv[u] : 0.0);
-                }
-            }
-            wave_sync();
-        }
-        uint64_t lm = ballot(lng);
-        while (lm) {
-            const int e = __ffsll((unsigned long long)lm) - 1;
-            lm &= lm - 1;
-            const int64_t eb0 = (int64_t)shfl(b0, e);
-            const int64_t elen = shfl(len, e);
-            const double ea = VALS ? shfl(a, e) : 0.0;
-            int last = INT32_MIN;  // CHECK: column of the entry before this step's first
-            for (int64_t q0 = 0; q0 < elen; q0 += U * kWave) {
-                int c[U];
-                T bv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t q = q0 + u * kWave + lane;
-                    c[u] = -1;
-                    bv[u] = T(0);
-                    if (q < elen) {
-                        c[u] = b_col[eb0 + q];
-                        if (VALS) bv[u] = b_val[eb0 + q];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (CHECK) {
-                        int prev = __shfl_up(c[u], 1, kWave);
-                        if (lane == 0) prev = last;
-                        if (c[u] >= 0 && prev > c[u]) *unsorted = true;
-                        last = __shfl(c[u], kWave - 1, kWave);
-                    }
-                    if (c[u] >= 0) fn(c[u], VALS ? ea * (double)bv[u] : 0.0);
-                }
-            }
-        }
+// The A entry a thread holds: the B row it names and the A value.
+struct LongEnt {
+    int64_t b0;    // first B entry of the named row
+    int64_t len;   // its length (0 for threads without an entry)
+    double a;
+};
+
+// Thread t's entry of block `blk` (entries blk * NT + t of the A row at rs).
+template <int NT, typename T, typename IdxT, bool VALS>
+__device__ __forceinline__ LongEnt long_entry(IdxT rs, int64_t nA, int blk, const int32_t* __restrict__ a_col,
+                                              const T* __restrict__ a_val, const IdxT* __restrict__ b_rp) {
+    LongEnt en{0, 0, 0.0};
+    const int64_t e = (int64_t)blk * NT + threadIdx.x;
+    if (e < nA) {
+        const int k = a_col[rs + e];
+        const IdxT x0 = b_rp[k];
+        const IdxT x1 = b_rp[k + 1];
+        en.b0 = (int64_t)x0;
+        en.len = (int64_t)x1 - (int64_t)x0;
+        if (VALS) en.a = (double)a_val[rs + e];
     }
+    return en;
 }
 
-// Walks a B row stored in column order (entries [0, elen) of col/val) from
-// entry qlo, U steps of 64 entries at a time, calling fn(col, a * val) for
-// the entries with columns in [clo, chi); stops after the step in which a
-// column reaches chi or the row ends.
-template <int U, typename T, typename Fn>
-__device__ __forceinline__ void chunk_walk(const int32_t* __restrict__ col, const T* __restrict__ val, int64_t qlo,
-                                           int64_t elen, int clo, int chi, double a, int lane, Fn&& fn) {
-    for (int64_t base = qlo; base < elen; base += U * kWave) {
-        int c[U];
-        T v[U];
+// Publishes every thread's range [q, q + len) (scaled by a) for a flattened
+// walk and returns the block's product count.  Collective: every thread of
+// the workgroup calls it.  The scan's first barrier also ends the walks of
+// the previous publication before the stage is overwritten.
+template <int NT, bool VALS>
+__device__ __forceinline__ int64_t flat_publish(FlatStage<NT, VALS>& st, int64_t q, int64_t len, double a,
+                                                long long* s_red) {
+    long long tot;
+    const long long ex = block_excl_scan_i64<NT>((long long)len, s_red, &tot);
+    st.pre[threadIdx.x] = ex;
+    st.qs[threadIdx.x] = q;
+    if constexpr (VALS) st.a[threadIdx.x] = a;
+    if (threadIdx.x == 0) st.pre[NT] = tot;
+    __syncthreads();
+    return tot;
+}
+
+// Calls fn(col, v) for every product of a published block (total products)
+// that this wavefront owns; v = a_e * b_kj in FP64 when VALS (else 0).
+// CHECK sets *unsorted when two consecutive entries of one B row are in
+// descending column order.
+template <int NT, typename T, bool VALS, bool SVALS, bool CHECK, typename Fn>
+__device__ __forceinline__ void flat_walk(const FlatStage<NT, SVALS>& st, int64_t total,
+                                          const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
+                                          int wave, int nwaves, Fn&& fn, bool* unsorted = nullptr) {
+    constexpr int U = kFlatU;
+    const int lane = lane_id();
+    for (int64_t s = (int64_t)wave * (kWave * U); s < total; s += (int64_t)nwaves * (kWave * U)) {
+        const int64_t p0 = s + (int64_t)lane * U;
+        int64_t q[U];
+        double a[U];
+        bool on[U], first[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t q = base + u * kWave + lane;
-            c[u] = INT32_MAX;
-            v[u] = T(0);
-            if (q < elen) {
-                c[u] = col[q];
-                v[u] = val[q];
+            q[u] = 0;
+            a[u] = 0.0;
+            on[u] = false;
+            first[u] = true;
+        }
+        if (p0 < total) {
+            // entry of p0: pre[lo] <= p0 < pre[hi] (pre[0] = 0, pre[NT] = total)
+            int lo = 0, hi = NT;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (st.pre[mid] <= p0) lo = mid; else hi = mid;
+            }
+            int e = lo;
+            int64_t eb = st.pre[e], nb = st.pre[e + 1];
+            int64_t base = st.qs[e] - eb;
+            double ea = 0.0;
+            if constexpr (SVALS) ea = st.a[e];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t pp = p0 + u;
+                if (pp < total) {
+                    // the run crosses into the next non-empty entry (pre[NT] = total > pp bounds it)
+                    while (pp >= nb) {
+                        ++e;
+                        eb = nb;
+                        nb = st.pre[e + 1];
+                        base = st.qs[e] - eb;
+                        if constexpr (SVALS) ea = st.a[e];
+                    }
+                    on[u] = true;
+                    q[u] = base + pp;
+                    a[u] = ea;
+                    first[u] = pp == eb;
+                }
+            }
+        }
+        int c[U];
+        T bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = -1;
+            bv[u] = T(0);
+            if (on[u]) {
+                c[u] = b_col[q[u]];
+                if (VALS) bv[u] = b_val[q[u]];
+            }
+        }
+        if (CHECK) {
+            // the product before this lane's first is lane - 1's last (for
+            // lane 0 it belongs to another step: read it)
+            int prev = __shfl_up(c[U - 1], 1, kWave);
+            if (lane == 0 && on[0] && !first[0]) prev = b_col[q[0] - 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pc = u == 0 ? prev : c[u - 1];
+                if (on[u] && !first[u] && pc > c[u]) *unsorted = true;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (c[u] >= clo && c[u] < chi) fn(c[u], a * (double)v[u]);
-        if (ballot(c[U - 1] < chi) != ~0ull) break;
+            if (on[u]) fn(c[u], VALS ? a[u] * (double)bv[u] : 0.0);
     }
 }
 
+// First position in [lo, hi) of the column-ordered B row at col whose column
+// is at least x (hi if none).
+__device__ __forceinline__ int64_t lower_col(const int32_t* __restrict__ col, int64_t lo, int64_t hi, int x) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 // Partial products of the A row [rs, rs + nA): sum of its entries' B-row lengths.
-template <typename IdxT>
+template <int NT, typename IdxT>
 __device__ __forceinline__ long long long_row_count(IdxT rs, int64_t nA, const int32_t* __restrict__ a_col,
                                                     const IdxT* __restrict__ b_rp, long long* s_red) {
     long long s = 0;
-    for (int64_t e = threadIdx.x; e < nA; e += kLongThreads) {
+    for (int64_t e = threadIdx.x; e < nA; e += NT) {
         const int k = a_col[rs + e];
         s += (long long)b_rp[k + 1] - (long long)b_rp[k];
     }
-    return block_sum_i64<kLongThreads>(s, s_red);
+    return block_sum_i64<NT>(s, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,10 +205,11 @@ __device__ __forceinline__ long long long_row_count(IdxT rs, int64_t nA, const i
 template <typename IdxT>
 __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P,
                                                           BatchMap bm) {
+    constexpr int NT = kLongThreads, NW = kLongWaves;
     __shared__ uint32_t s_bits[kLongSegWords];
-    __shared__ LongChunk<IdxT> s_tb[kLongWaves];
-    __shared__ long long s_red[kLongWaves];
-    __shared__ int s_redi[kLongWaves];
+    __shared__ FlatStage<NT, false> s_st;
+    __shared__ long long s_red[NW];
+    __shared__ int s_redi[NW];
     __shared__ int s_next;
 
     const int w = threadIdx.x / kWave;
@@ -213,32 +226,54 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
         const int64_t i = ent.y;
         const IdxT rs = p.a_rp[i];
         const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
-        const long long prods = long_row_count<IdxT>(rs, nA, p.a_col, p.b_rp, s_red);
+        const int nblk = (int)((nA + NT - 1) / NT);
+        const float* no_val = nullptr;
+        // a row of one block is published once for all its walks
+        int64_t tot1 = 0;
+        long long prods;
+        if (nblk == 1) {
+            const LongEnt en = long_entry<NT, float, IdxT, false>(rs, nA, 0, p.a_col, no_val, p.b_rp);
+            tot1 = flat_publish<NT, false>(s_st, en.b0, en.len, 0.0, s_red);
+            prods = (long long)tot1;
+        } else {
+            prods = long_row_count<NT, IdxT>(rs, nA, p.a_col, p.b_rp, s_red);
+        }
+        auto walk_all = [&](auto&& fn, bool* unsorted) {
+            if (nblk == 1) {
+                flat_walk<NT, float, false, false, true>(s_st, tot1, p.b_col, no_val, w, NW, fn, unsorted);
+                return;
+            }
+            for (int b = 0; b < nblk; ++b) {
+                const LongEnt en = long_entry<NT, float, IdxT, false>(rs, nA, b, p.a_col, no_val, p.b_rp);
+                const int64_t tot = flat_publish<NT, false>(s_st, en.b0, en.len, 0.0, s_red);
+                flat_walk<NT, float, false, false, true>(s_st, tot, p.b_col, no_val, w, NW, fn, unsorted);
+            }
+        };
 
         int lo = 0;
         int64_t span = p.n;
+        bool unsorted = false;
         if (p.n > seg_cols) {
             int cmin = INT32_MAX, cmax = -1;
-            long_row_products<IdxT, float, false>(rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, nullptr, w, kLongWaves,
-                                                  s_tb[w], [&](int col, double) {
-                                                      cmin = min(cmin, col);
-                                                      cmax = max(cmax, col);
-                                                  });
-            cmin = block_min_i32<kLongThreads>(cmin, s_redi);
-            cmax = block_max_i32<kLongThreads>(cmax, s_redi);
+            walk_all(
+                [&](int col, double) {
+                    cmin = min(cmin, col);
+                    cmax = max(cmax, col);
+                },
+                &unsorted);
+            cmin = block_min_i32<NT>(cmin, s_redi);
+            cmax = block_max_i32<NT>(cmax, s_redi);
             lo = cmin;
             span = (cmax >= cmin) ? (int64_t)cmax - cmin + 1 : 0;
         }
         long long nnz = 0;
-        bool unsorted = false;
         for (int64_t s0 = 0; s0 < span; s0 += seg_cols) {
             const int seg_lo = lo + (int)s0;
             const int seg_w = (int)((min((int64_t)seg_cols, span - s0) + 31) >> 5);
             const int seg_hi = seg_lo + seg_w * 32;
-            for (int x = threadIdx.x; x < seg_w; x += kLongThreads) s_bits[x] = 0u;
+            for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
             __syncthreads();
-            long_row_products<IdxT, float, false, true>(
-                rs, nA, p.a_col, nullptr, p.b_rp, p.b_col, nullptr, w, kLongWaves, s_tb[w],
+            walk_all(
                 [&](int col, double) {
                     if (col >= seg_lo && col < seg_hi) {
                         const int d = col - seg_lo;
@@ -248,23 +283,23 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
                 &unsorted);
             __syncthreads();
             long long pc = 0;
-            for (int x = threadIdx.x; x < seg_w; x += kLongThreads) pc += __popc(s_bits[x]);
-            nnz += block_sum_i64<kLongThreads>(pc, s_red);
+            for (int x = threadIdx.x; x < seg_w; x += NT) pc += __popc(s_bits[x]);
+            nnz += block_sum_i64<NT>(pc, s_red);
         }
         if (p.n <= seg_cols && span > 0) {
             // one segment from column 0: narrow the window to the set bits
             // (the numeric pass then zeroes, scans and emits fewer words)
             const int seg_w = (int)((span + 31) >> 5);
             int cmin = INT32_MAX, cmax = -1;
-            for (int x = threadIdx.x; x < seg_w; x += kLongThreads) {
+            for (int x = threadIdx.x; x < seg_w; x += NT) {
                 const uint32_t bw = s_bits[x];
                 if (bw) {
                     cmin = min(cmin, x * 32 + __ffs(bw) - 1);
                     cmax = max(cmax, x * 32 + 31 - __clz(bw));
                 }
             }
-            cmin = block_min_i32<kLongThreads>(cmin, s_redi);
-            cmax = block_max_i32<kLongThreads>(cmax, s_redi);
+            cmin = block_min_i32<NT>(cmin, s_redi);
+            cmax = block_max_i32<NT>(cmax, s_redi);
             lo = cmax >= 0 ? cmin : 0;
             span = cmax >= 0 ? (int64_t)cmax - cmin + 1 : 0;
         }
@@ -292,13 +327,13 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 // and a popcount, (3) accumulation by rank, (4) columns written from the
 // bitmap in ascending order.  Accumulation:
 //  - a segment with at most V = group_lds_values (<= 8192) entries is summed
-//    in LDS in one walk of the products;
+//    in LDS in one flattened walk of the products;
 //  - a larger segment is cut into nch chunks of V consecutive ranks (a column
 //    range each).  If the long B rows are in column order (checked by the
-//    symbolic pass), each chunk is summed in LDS and written to C: every lane
-//    binary-searches where the chunk's column range starts in its A entry's
-//    B row; rows averaging fewer than 64 entries per chunk are then walked by
-//    their own lane, longer ones by the whole wavefront, until the range ends;
+//    symbolic pass), each chunk is summed in LDS and written to C: the thread
+//    holding an A entry binary-searches where the chunk's column range ends
+//    in its B row (it starts where the previous chunk's ended), and the
+//    ranges of all entries are walked flattened;
 //  - if a long B row is not in column order, every product of the segment is
 //    added with FP64 atomics into device memory: C's own values for FP64, a
 //    per-workgroup FP64 buffer for FP32 (rounded once on the copy out).  Only
@@ -311,32 +346,58 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
     __shared__ uint32_t s_bits[kLongSegWords];
     __shared__ uint32_t s_pfx[kLongSegWords];
     __shared__ double s_vals[kLongVals];
-    __shared__ LongChunk<IdxT> s_tb[NW];
+    __shared__ FlatStage<NT, true> s_st;
     __shared__ long long s_red[NW];
     __shared__ int s_bound[kLongMaxChunks + 1];
     __shared__ int s_next;
 
     const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
     const int nL = (int)*bm.n_long;
     for (;;) {
         if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[1], 1u);
         __syncthreads();
-        const int j = s_next;
+        const int j = uniform_i32(s_next);
         if (j >= nL) break;
         const int2 ent = bm.long_list[j];
-        const NumArgs<T, IdxT, IdxC> p = P ? P[ent.x] : p0;
-        const int seg_cols = p.th.group_lds_span;
-        const int V = min(max(p.th.group_lds_values, kLongMinVals), kLongVals);
-        const bool sorted_b = (p.ctr->bad_csr & kUnsortedB) == 0u;
-        const int64_t i = ent.y;
-        const IdxT rs = p.a_rp[i];
-        const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
+        const NumArgs<T, IdxT, IdxC> p = P ? P[uniform_i32(ent.x)] : p0;
+        const int seg_cols = uniform_i32(p.th.group_lds_span);
+        const int V = min(max(uniform_i32(p.th.group_lds_values), kLongMinVals), kLongVals);
+        const bool sorted_b = (uniform_i32((int)p.ctr->bad_csr) & kUnsortedB) == 0u;
+        const int64_t i = uniform_i32(ent.y);
+        const IdxT rs = uniform(p.a_rp[i]);
+        const int64_t nA = uniform((int64_t)p.a_rp[i + 1]) - (int64_t)rs;
+        const int nblk = (int)((nA + NT - 1) / NT);
         const int2 wn = p.win[i];
-        const int lo = wn.x;
-        const int64_t span = wn.y;
-        const int64_t cb = (int64_t)p.c_rp[i];
-        const int64_t nc_row = (int64_t)p.c_rp[i + 1] - cb;
+        const int lo = uniform_i32(wn.x);
+        const int64_t span = uniform_i32(wn.y);
+        const int64_t cb = uniform((int64_t)p.c_rp[i]);
+        const int64_t nc_row = uniform((int64_t)p.c_rp[i + 1]) - cb;
+
+        // a row of one block keeps its entry in registers and its full
+        // ranges published until a chunked accumulation replaces them
+        LongEnt en1{0, 0, 0.0};
+        int64_t tot1 = 0;
+        bool full1 = false;
+        if (nblk == 1) en1 = long_entry<NT, T, IdxT, true>(rs, nA, 0, p.a_col, p.a_val, p.b_rp);
+        auto walk_all = [&](auto vals_tag, auto&& fn) {
+            constexpr bool VL = decltype(vals_tag)::value;
+            if (nblk == 1) {
+                if (!full1) {
+                    tot1 = flat_publish<NT, true>(s_st, en1.b0, en1.len, en1.a, s_red);
+                    full1 = true;
+                }
+                flat_walk<NT, T, VL, true, false>(s_st, tot1, p.b_col, p.b_val, w, NW, fn);
+                return;
+            }
+            for (int b = 0; b < nblk; ++b) {
+                const LongEnt en = long_entry<NT, T, IdxT, true>(rs, nA, b, p.a_col, p.a_val, p.b_rp);
+                const int64_t tot = flat_publish<NT, true>(s_st, en.b0, en.len, en.a, s_red);
+                flat_walk<NT, T, VL, true, false>(s_st, tot, p.b_col, p.b_val, w, NW, fn);
+            }
+        };
+        using NoVals = std::integral_constant<bool, false>;
+        using Vals = std::integral_constant<bool, true>;
+
         int64_t off = 0;
         for (int64_t s0 = 0; s0 < span; s0 += seg_cols) {
             const int seg_lo = lo + (int)s0;
@@ -344,13 +405,12 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
             const int seg_hi = seg_lo + seg_w * 32;
             for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
             __syncthreads();
-            long_row_products<IdxT, T, false>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
-                                              [&](int col, double) {
-                                                  if (col >= seg_lo && col < seg_hi) {
-                                                      const int d = col - seg_lo;
-                                                      atomicOr(&s_bits[d >> 5], 1u << (d & 31));
-                                                  }
-                                              });
+            walk_all(NoVals{}, [&](int col, double) {
+                if (col >= seg_lo && col < seg_hi) {
+                    const int d = col - seg_lo;
+                    atomicOr(&s_bits[d >> 5], 1u << (d & 31));
+                }
+            });
             __syncthreads();
             // thread t owns words [t*per, t*per + per)
             const int per = (seg_w + NT - 1) / NT;
@@ -379,11 +439,9 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 // the whole segment in LDS
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) s_vals[x] = 0.0;
                 __syncthreads();
-                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
-                                                 [&](int col, double v) {
-                                                     if (col >= seg_lo && col < seg_hi)
-                                                         atomicAdd(&s_vals[rank_of(col)], v);
-                                                 });
+                walk_all(Vals{}, [&](int col, double v) {
+                    if (col >= seg_lo && col < seg_hi) atomicAdd(&s_vals[rank_of(col)], v);
+                });
                 __syncthreads();
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)s_vals[x];
             } else if (sorted_b) {
@@ -407,83 +465,26 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                     }
                 }
                 __syncthreads();
+                // with one block, each thread's position in its B row carries
+                // from one chunk to the next (the chunk's range starts there)
+                int64_t cur1 = 0;
                 for (int c = 0; c < nch; ++c) {
                     const int clo = s_bound[c], chi = s_bound[c + 1];
                     const int r0 = c * V, rn = min(V, seg_nnz - r0);
                     for (int x = threadIdx.x; x < rn; x += NT) s_vals[x] = 0.0;
-                    __syncthreads();
                     auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
-                    for (int64_t ch = (int64_t)w * kWave; ch < nA; ch += (int64_t)NW * kWave) {
-                        const int cnt = (int)min((int64_t)kWave, nA - ch);
-                        int64_t b0 = 0, len = 0;
-                        double a = 0.0;
-                        if (lane < cnt) {
-                            const int k = p.a_col[rs + ch + lane];
-                            const IdxT x0 = p.b_rp[k];
-                            b0 = (int64_t)x0;
-                            len = (int64_t)p.b_rp[k + 1] - (int64_t)x0;
-                            a = (double)p.a_val[rs + ch + lane];
-                        }
-                        // every lane finds where the chunk's column range starts in its
-                        // own B row (binary search, the 64 searches side by side)
-                        int64_t cur = 0;
-                        {
-                            int64_t hi = len;
-                            while (cur < hi) {
-                                const int64_t mid = (cur + hi) >> 1;
-                                if (p.b_col[b0 + mid] < clo) cur = mid + 1; else hi = mid;
-                            }
-                        }
-                        // B rows averaging fewer than 64 entries per chunk: each lane
-                        // walks its own row until the range ends, four entries per
-                        // step (their loads issued together; in a sorted row the
-                        // entries below chi are a prefix of the four)
-                        const bool heavy = len >= (int64_t)kWave * nch;
-                        bool act = !heavy && cur < len;
-                        while (ballot(act)) {
-                            if (act) {
-                                int c4[4];
-                                T v4[4];
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) {
-                                    c4[u] = INT32_MAX;
-                                    v4[u] = T(0);
-                                    if (cur + u < len) {
-                                        c4[u] = p.b_col[b0 + cur + u];
-                                        v4[u] = p.b_val[b0 + cur + u];
-                                    }
-                                }
-                                int taken = 0;
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) {
-                                    if (c4[u] < chi) {
-                                        add(c4[u], a * (double)v4[u]);
-                                        ++taken;
-                                    }
-                                }
-                                cur += taken;
-                                act = taken == 4 && cur < len;
-                            }
-                        }
-                        // the others: the whole wavefront walks one row at a time, with
-                        // four, two or one 64-entry steps of loads in flight as the row
-                        // averages >= 256, >= 128 or fewer entries per chunk
-                        uint64_t hm = ballot(heavy);
-                        while (hm) {
-                            const int e = __ffsll((unsigned long long)hm) - 1;
-                            hm &= hm - 1;
-                            const int64_t eb0 = shfl(b0, e);
-                            const int64_t elen = shfl(len, e);
-                            const int64_t q0 = shfl(cur, e);
-                            const double ea = shfl(a, e);
-                            if (elen >= 256 * (int64_t)nch)
-                                chunk_walk<4, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
-                            else if (elen >= 128 * (int64_t)nch)
-                                chunk_walk<2, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
-                            else
-                                chunk_walk<1, T>(p.b_col + eb0, p.b_val + eb0, q0, elen, clo, chi, ea, lane, add);
-                        }
+                    for (int b = 0; b < nblk; ++b) {
+                        const LongEnt en = nblk == 1 ? en1 : long_entry<NT, T, IdxT, true>(rs, nA, b, p.a_col,
+                                                                                           p.a_val, p.b_rp);
+                        const int32_t* brow = p.b_col + en.b0;
+                        const int64_t qlo = (nblk == 1 && c > 0) ? cur1 : lower_col(brow, 0, en.len, clo);
+                        const int64_t qhi = lower_col(brow, qlo, en.len, chi);
+                        cur1 = qhi;
+                        // publishing (its barriers) also orders the zeroing above before the adds
+                        const int64_t tot = flat_publish<NT, true>(s_st, en.b0 + qlo, qhi - qlo, en.a, s_red);
+                        flat_walk<NT, T, true, true, false>(s_st, tot, p.b_col, p.b_val, w, NW, add);
                     }
+                    full1 = false;
                     __syncthreads();
                     for (int x = threadIdx.x; x < rn; x += NT) p.c_val[cb + off + r0 + x] = (T)s_vals[x];
                     __syncthreads();
@@ -499,13 +500,10 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 for (int x = threadIdx.x; x < seg_nnz; x += NT) acc[x] = 0.0;
                 __threadfence_block();
                 __syncthreads();
-                long_row_products<IdxT, T, true>(rs, nA, p.a_col, p.a_val, p.b_rp, p.b_col, p.b_val, w, NW, s_tb[w],
-                                                 [&](int col, double v) {
-                                                     if (col >= seg_lo && col < seg_hi)
-                                                         __hip_atomic_fetch_add(&acc[rank_of(col)], v,
-                                                                                __ATOMIC_RELAXED,
-                                                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                                                 });
+                walk_all(Vals{}, [&](int col, double v) {
+                    if (col >= seg_lo && col < seg_hi)
+                        __hip_atomic_fetch_add(&acc[rank_of(col)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                });
                 if constexpr (sizeof(T) != sizeof(double)) {
                     // the adds of every wavefront are complete before the buffer is read
                     // back (all of the workgroup's accesses go through one CU, so a
