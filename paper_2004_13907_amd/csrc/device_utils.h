@@ -151,6 +151,26 @@ __device__ __forceinline__ long long block_excl_scan_i64(long long v, long long*
     return before + incl - v;
 }
 
+// The same scan with one barrier: the partials go to `buf`, which no thread
+// may still be reading from an earlier call (the caller places a workgroup
+// barrier between two calls on one buffer).
+template <int NT>
+__device__ __forceinline__ long long block_excl_scan1_i64(long long v, long long* buf, long long* total) {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const long long incl = wave_incl_scan_i64(v);
+    if (lane == kWave - 1) buf[w] = incl;
+    __syncthreads();
+    long long before = 0, all = 0;
+#pragma unroll
+    for (int x = 0; x < NT / kWave; ++x) {
+        const long long t = buf[x];
+        before += (x < w) ? t : 0;
+        all += t;
+    }
+    *total = all;
+    return before + incl - v;
+}
+
 // Maps hardware workgroup ids (dispatched round-robin over the XCDs) to
 // logical ids so that each XCD processes one contiguous range of logical ids;
 // neighbouring rows then share that XCD's L2.  A bijection on [0, n).

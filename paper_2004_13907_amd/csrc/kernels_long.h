@@ -11,10 +11,11 @@
 // Flattened walks.  The products of a row form one index space: A entry e
 // (thread e of the workgroup holds it) covers the products
 // [pre[e], pre[e + 1]), pre being the exclusive prefix sum of the lengths of
-// the B rows the entries name.  Each wavefront takes steps of 64 * kFlatU
-// consecutive products and each lane kFlatU consecutive ones of a step; a
-// lane finds the entry of its first product by a binary search over pre in
-// LDS and moves to the next entry when its run crosses one.  Every wavefront
+// the B rows the entries name.  Each wavefront takes steps of 64 * U
+// consecutive products, lane l the products 64 u + l of the step (u < U), so
+// that every load instruction reads 64 consecutive B entries; a lane finds
+// the entry of a product by a binary search over pre in LDS when the product
+// passes the end of its previous one.  Every wavefront
 // of the workgroup thus gets the same share of the row whatever the lengths
 // of its B rows (a row of A·Aᵀ on a power-law matrix typically has a dozen
 // entries, some naming B rows of tens of thousands of entries).  Rows with
@@ -41,7 +42,8 @@ constexpr int kLongSegWords = 8192;     // 262144 columns per window segment
 constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS
 constexpr int kLongMinVals = 256;       // smallest rank chunk accepted
 constexpr int kLongMaxChunks = kLongSegWords * 32 / kLongMinVals;
-constexpr int kFlatU = 4;               // consecutive products per lane and step of a flattened walk
+constexpr int kFlatU = 4;               // products per lane and step of a flattened walk that reads values
+constexpr int kFlatUCols = 8;           // ... of one that reads columns only
 constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a B row read by a long row is not in column order
 
 // One block of (at most NT) A entries of a long row, published for a
@@ -61,13 +63,14 @@ struct LongEnt {
     double a;
 };
 
-// Thread t's entry of block `blk` (entries blk * NT + t of the A row at rs).
-template <int NT, typename T, typename IdxT, bool VALS>
+// Thread t's entry of block `blk` (entries blk * NB + t of the A row at rs;
+// threads from NB on hold none).
+template <int NB, typename T, typename IdxT, bool VALS>
 __device__ __forceinline__ LongEnt long_entry(IdxT rs, int64_t nA, int blk, const int32_t* __restrict__ a_col,
                                               const T* __restrict__ a_val, const IdxT* __restrict__ b_rp) {
     LongEnt en{0, 0, 0.0};
-    const int64_t e = (int64_t)blk * NT + threadIdx.x;
-    if (e < nA) {
+    const int64_t e = (int64_t)blk * NB + threadIdx.x;
+    if ((int)threadIdx.x < NB && e < nA) {
         const int k = a_col[rs + e];
         const IdxT x0 = b_rp[k];
         const IdxT x1 = b_rp[k + 1];
@@ -78,74 +81,81 @@ __device__ __forceinline__ LongEnt long_entry(IdxT rs, int64_t nA, int blk, cons
     return en;
 }
 
-// Publishes every thread's range [q, q + len) (scaled by a) for a flattened
-// walk and returns the block's product count.  Collective: every thread of
-// the workgroup calls it.  The scan's first barrier also ends the walks of
-// the previous publication before the stage is overwritten.
-template <int NT, bool VALS>
-__device__ __forceinline__ int64_t flat_publish(FlatStage<NT, VALS>& st, int64_t q, int64_t len, double a,
-                                                long long* s_red) {
+// Publishes the range [q, q + len) (scaled by a) of each of the first NB
+// threads (the others pass len = 0) for a flattened walk and returns the
+// block's product count.  Collective: every thread of the workgroup (NT)
+// calls it.  The scan's barrier also ends the walks of the previous
+// publication before the stage is overwritten.  `buf` (NT / 64 partials)
+// serves publications only: the barrier that ends each publication
+// separates it from the next.
+template <int NT, int NB, bool VALS>
+__device__ __forceinline__ int64_t flat_publish(FlatStage<NB, VALS>& st, int64_t q, int64_t len, double a,
+                                                long long* buf) {
     long long tot;
-    const long long ex = block_excl_scan_i64<NT>((long long)len, s_red, &tot);
-    st.pre[threadIdx.x] = ex;
-    st.qs[threadIdx.x] = q;
-    if constexpr (VALS) st.a[threadIdx.x] = a;
-    if (threadIdx.x == 0) st.pre[NT] = tot;
+    const long long ex = block_excl_scan1_i64<NT>((long long)len, buf, &tot);
+    if ((int)threadIdx.x < NB) {
+        st.pre[threadIdx.x] = ex;
+        st.qs[threadIdx.x] = q;
+        if constexpr (VALS) st.a[threadIdx.x] = a;
+    }
+    if (threadIdx.x == 0) st.pre[NB] = tot;
     __syncthreads();
     return tot;
 }
 
-// Calls fn(col, v) for every product of a published block (total products)
-// that this wavefront owns; v = a_e * b_kj in FP64 when VALS (else 0).
-// CHECK sets *unsorted when two consecutive entries of one B row are in
-// descending column order.
-template <int NT, typename T, bool VALS, bool SVALS, bool CHECK, typename Fn>
-__device__ __forceinline__ void flat_walk(const FlatStage<NT, SVALS>& st, int64_t total,
+// Entry of product p among entries [lo, hi) of a published block: the e with
+// pre[e] <= p < pre[e + 1], given pre[lo] <= p < pre[hi].
+template <int NT, bool SVALS>
+__device__ __forceinline__ int flat_find(const FlatStage<NT, SVALS>& st, int lo, int hi, int64_t p) {
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (st.pre[mid] <= p) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Calls fn(col, v) for every product of a published block (ne entries,
+// total products) that this wavefront owns; v = a_e * b_kj in FP64 when VALS
+// (else 0).  The wavefront takes steps of 64 * U consecutive products; in
+// step s, lane l takes products s + 64 u + l (u < U), so that each of the
+// U loads of a step reads 64 consecutive B entries wherever the step lies
+// inside one B row.  A lane's products only move forward: it keeps the
+// bounds of its current entry and searches the later entries only when a
+// product passes the end of it.  CHECK sets *unsorted when two consecutive
+// entries of one B row are in descending column order.
+template <int U, int NT, typename T, bool VALS, bool SVALS, bool CHECK, typename Fn>
+__device__ __forceinline__ void flat_walk(const FlatStage<NT, SVALS>& st, int ne, int64_t total,
                                           const int32_t* __restrict__ b_col, const T* __restrict__ b_val,
                                           int wave, int nwaves, Fn&& fn, bool* unsorted = nullptr) {
-    constexpr int U = kFlatU;
     const int lane = lane_id();
+    // this lane's current entry e: products [eb, nb), B entry of product p = base + p
+    int e = 0;
+    int64_t eb = 0, nb = st.pre[1], base = st.qs[0];
+    double ea = 0.0;
+    if constexpr (SVALS) ea = st.a[0];
     for (int64_t s = (int64_t)wave * (kWave * U); s < total; s += (int64_t)nwaves * (kWave * U)) {
-        const int64_t p0 = s + (int64_t)lane * U;
         int64_t q[U];
         double a[U];
         bool on[U], first[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            const int64_t p = s + u * kWave + lane;
+            on[u] = p < total;
             q[u] = 0;
             a[u] = 0.0;
-            on[u] = false;
             first[u] = true;
-        }
-        if (p0 < total) {
-            // entry of p0: pre[lo] <= p0 < pre[hi] (pre[0] = 0, pre[NT] = total)
-            int lo = 0, hi = NT;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (st.pre[mid] <= p0) lo = mid; else hi = mid;
-            }
-            int e = lo;
-            int64_t eb = st.pre[e], nb = st.pre[e + 1];
-            int64_t base = st.qs[e] - eb;
-            double ea = 0.0;
-            if constexpr (SVALS) ea = st.a[e];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t pp = p0 + u;
-                if (pp < total) {
-                    // the run crosses into the next non-empty entry (pre[NT] = total > pp bounds it)
-                    while (pp >= nb) {
-                        ++e;
-                        eb = nb;
-                        nb = st.pre[e + 1];
-                        base = st.qs[e] - eb;
-                        if constexpr (SVALS) ea = st.a[e];
-                    }
-                    on[u] = true;
-                    q[u] = base + pp;
-                    a[u] = ea;
-                    first[u] = pp == eb;
+            if (on[u]) {
+                if (p >= nb) {
+                    // pre[e + 1] = nb <= p < total = pre[ne]
+                    e = flat_find(st, e + 1, ne, p);
+                    eb = st.pre[e];
+                    nb = st.pre[e + 1];
+                    base = st.qs[e] - eb;
+                    if constexpr (SVALS) ea = st.a[e];
                 }
+                q[u] = base + p;
+                a[u] = ea;
+                first[u] = p == eb;
             }
         }
         int c[U];
@@ -160,14 +170,18 @@ __device__ __forceinline__ void flat_walk(const FlatStage<NT, SVALS>& st, int64_
             }
         }
         if (CHECK) {
-            // the product before this lane's first is lane - 1's last (for
-            // lane 0 it belongs to another step: read it)
-            int prev = __shfl_up(c[U - 1], 1, kWave);
-            if (lane == 0 && on[0] && !first[0]) prev = b_col[q[0] - 1];
+            // the product before (u, l) is (u, l - 1); before (u, 0) it is
+            // (u - 1, 63), and before (0, 0) it lies in an earlier step: read it
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int pc = u == 0 ? prev : c[u - 1];
-                if (on[u] && !first[u] && pc > c[u]) *unsorted = true;
+                int prev = __shfl_up(c[u], 1, kWave);
+                if (u > 0) {
+                    const int last = __shfl(c[u - 1], kWave - 1, kWave);
+                    if (lane == 0) prev = last;
+                } else if (lane == 0 && on[0] && !first[0]) {
+                    prev = b_col[q[0] - 1];
+                }
+                if (on[u] && !first[u] && prev > c[u]) *unsorted = true;
             }
         }
 #pragma unroll
@@ -201,59 +215,76 @@ __device__ __forceinline__ long long long_row_count(IdxT rs, int64_t nA, const i
 // ---------------------------------------------------------------------------
 // Symbolic pass for the long-row list: nnz(C_i) and the column window of each
 // long row.  The window is [0, n) when n fits one segment, else the row's
-// [min column, max column] (one extra walk of the products).
+// [min column, max column] (one extra walk of the products).  The segment
+// bitmap is all zero between segments: its words are cleared as they are
+// counted.
 template <typename IdxT>
 __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P,
                                                           BatchMap bm) {
     constexpr int NT = kLongThreads, NW = kLongWaves;
     __shared__ uint32_t s_bits[kLongSegWords];
     __shared__ FlatStage<NT, false> s_st;
-    __shared__ long long s_red[NW];
+    __shared__ long long s_pub[NW];      // partials of the publications
+    __shared__ long long s_red[NW];      // partials of the other reductions
     __shared__ int s_redi[NW];
-    __shared__ int s_next;
+    __shared__ long long s_cnt[NW];      // per-segment count, first and last set column
+    __shared__ int s_cmin[NW], s_cmax[NW];
+    __shared__ int s_next[2];
 
     const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
     const int nL = (int)*bm.n_long;
     if (nL == 0) return;   // the usual case on regular inputs: leave before touching the queue
-    for (;;) {
-        if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[0], 1u);
-        __syncthreads();
-        const int j = s_next;
+    for (int x = threadIdx.x; x < kLongSegWords; x += NT) s_bits[x] = 0u;
+    if (threadIdx.x == 0) s_next[0] = (int)atomicAdd(&bm.queue[0], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int j = uniform_i32(s_next[it & 1]);
         if (j >= nL) break;
+        // take the next row now, so that its queue latency overlaps this one
+        // (read after this row's barriers; the slot alternates because a
+        // thread may still be reading this row's slot)
+        if (threadIdx.x == 0) s_next[(it + 1) & 1] = (int)atomicAdd(&bm.queue[0], 1u);
         const int2 ent = bm.long_list[j];
-        const SymArgs<IdxT> p = P ? P[ent.x] : p0;
-        const int seg_cols = p.th.group_lds_span;
-        const int64_t i = ent.y;
-        const IdxT rs = p.a_rp[i];
-        const int64_t nA = (int64_t)p.a_rp[i + 1] - (int64_t)rs;
+        const SymArgs<IdxT> p = P ? P[uniform_i32(ent.x)] : p0;
+        const int seg_cols = uniform_i32(p.th.group_lds_span);
+        const int64_t i = uniform_i32(ent.y);
+        const IdxT rs = uniform(p.a_rp[i]);
+        const int64_t nA = uniform((int64_t)p.a_rp[i + 1]) - (int64_t)rs;
         const int nblk = (int)((nA + NT - 1) / NT);
         const float* no_val = nullptr;
-        // a row of one block is published once for all its walks
+        // a row of one block is published once for all its walks (the
+        // publication's barriers also order the previous row's clearing of
+        // the bitmap before this row's first walk)
         int64_t tot1 = 0;
         long long prods;
         if (nblk == 1) {
             const LongEnt en = long_entry<NT, float, IdxT, false>(rs, nA, 0, p.a_col, no_val, p.b_rp);
-            tot1 = flat_publish<NT, false>(s_st, en.b0, en.len, 0.0, s_red);
+            tot1 = flat_publish<NT, NT, false>(s_st, en.b0, en.len, 0.0, s_pub);
             prods = (long long)tot1;
         } else {
             prods = long_row_count<NT, IdxT>(rs, nA, p.a_col, p.b_rp, s_red);
         }
         auto walk_all = [&](auto&& fn, bool* unsorted) {
             if (nblk == 1) {
-                flat_walk<NT, float, false, false, true>(s_st, tot1, p.b_col, no_val, w, NW, fn, unsorted);
+                flat_walk<kFlatUCols, NT, float, false, false, true>(s_st, (int)nA, tot1, p.b_col, no_val, w, NW, fn,
+                                                                     unsorted);
                 return;
             }
             for (int b = 0; b < nblk; ++b) {
                 const LongEnt en = long_entry<NT, float, IdxT, false>(rs, nA, b, p.a_col, no_val, p.b_rp);
-                const int64_t tot = flat_publish<NT, false>(s_st, en.b0, en.len, 0.0, s_red);
-                flat_walk<NT, float, false, false, true>(s_st, tot, p.b_col, no_val, w, NW, fn, unsorted);
+                const int64_t tot = flat_publish<NT, NT, false>(s_st, en.b0, en.len, 0.0, s_pub);
+                const int ne = (int)min((int64_t)NT, nA - (int64_t)b * NT);
+                flat_walk<kFlatUCols, NT, float, false, false, true>(s_st, ne, tot, p.b_col, no_val, w, NW, fn,
+                                                                     unsorted);
             }
         };
 
         int lo = 0;
         int64_t span = p.n;
         bool unsorted = false;
-        if (p.n > seg_cols) {
+        const bool one_seg = p.n <= seg_cols;
+        if (!one_seg) {
             int cmin = INT32_MAX, cmax = -1;
             walk_all(
                 [&](int col, double) {
@@ -267,12 +298,12 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             span = (cmax >= cmin) ? (int64_t)cmax - cmin + 1 : 0;
         }
         long long nnz = 0;
+        int first = INT32_MAX, last = -1;
         for (int64_t s0 = 0; s0 < span; s0 += seg_cols) {
+            if (s0 > 0) __syncthreads();   // the previous segment's words are clear
             const int seg_lo = lo + (int)s0;
             const int seg_w = (int)((min((int64_t)seg_cols, span - s0) + 31) >> 5);
             const int seg_hi = seg_lo + seg_w * 32;
-            for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
-            __syncthreads();
             walk_all(
                 [&](int col, double) {
                     if (col >= seg_lo && col < seg_hi) {
@@ -282,30 +313,46 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
                 },
                 &unsorted);
             __syncthreads();
+            // set bits, and the first and last set column (for a window of
+            // one segment from column 0, narrowed below), clearing each word
             long long pc = 0;
-            for (int x = threadIdx.x; x < seg_w; x += NT) pc += __popc(s_bits[x]);
-            nnz += block_sum_i64<NT>(pc, s_red);
-        }
-        if (p.n <= seg_cols && span > 0) {
-            // one segment from column 0: narrow the window to the set bits
-            // (the numeric pass then zeroes, scans and emits fewer words)
-            const int seg_w = (int)((span + 31) >> 5);
             int cmin = INT32_MAX, cmax = -1;
             for (int x = threadIdx.x; x < seg_w; x += NT) {
                 const uint32_t bw = s_bits[x];
                 if (bw) {
+                    pc += __popc(bw);
                     cmin = min(cmin, x * 32 + __ffs(bw) - 1);
                     cmax = max(cmax, x * 32 + 31 - __clz(bw));
+                    s_bits[x] = 0u;
                 }
             }
-            cmin = block_min_i32<NT>(cmin, s_redi);
-            cmax = block_max_i32<NT>(cmax, s_redi);
-            lo = cmax >= 0 ? cmin : 0;
-            span = cmax >= 0 ? (int64_t)cmax - cmin + 1 : 0;
+            pc = wave_sum_i64(pc);
+            cmin = wave_min_i32(cmin);
+            cmax = wave_max_i32(cmax);
+            if (lane == 0) {
+                s_cnt[w] = pc;
+                s_cmin[w] = cmin;
+                s_cmax[w] = cmax;
+            }
+            __syncthreads();
+            long long sn = 0;
+#pragma unroll
+            for (int x = 0; x < NW; ++x) {
+                sn += s_cnt[x];
+                first = min(first, s_cmin[x]);
+                last = max(last, s_cmax[x]);
+            }
+            nnz += sn;
+        }
+        if (one_seg && span > 0) {
+            // one segment from column 0: narrow the window to the set bits
+            // (the numeric pass then scans and emits fewer words)
+            lo = last >= 0 ? first : 0;
+            span = last >= 0 ? (int64_t)last - first + 1 : 0;
         }
         // the numeric pass walks the B rows of long rows in column order only
         // when they are stored that way
-        if (ballot(unsorted) && lane_id() == 0) atomicOr(&p.ctr->bad_csr, kUnsortedB);
+        if (ballot(unsorted) && lane == 0) atomicOr(&p.ctr->bad_csr, kUnsortedB);
         if (threadIdx.x == 0) {
             p.rnnz[i] = (int32_t)nnz;
             p.win[i] = make_int2(lo, (int)span);
@@ -315,7 +362,8 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             atomicMax(&p.ctr->max_nnz, (unsigned)nnz);
             atomicMax(&p.ctr->max_group_nnz, (unsigned)nnz);
         }
-        __syncthreads();
+        // s_cnt, s_cmin, s_cmax are read again only after the next row's
+        // publication and walk (two barriers on)
     }
 }
 
@@ -330,34 +378,47 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 //    in LDS in one flattened walk of the products;
 //  - a larger segment is cut into nch chunks of V consecutive ranks (a column
 //    range each).  If the long B rows are in column order (checked by the
-//    symbolic pass), each chunk is summed in LDS and written to C: the thread
-//    holding an A entry binary-searches where the chunk's column range ends
-//    in its B row (it starts where the previous chunk's ended), and the
-//    ranges of all entries are walked flattened;
+//    symbolic pass), each chunk is summed in LDS and written to C; where
+//    every chunk boundary falls in every B row of the row is found first
+//    with all binary searches side by side (one per boundary and A entry,
+//    positions kept in LDS), then the chunks' ranges are walked flattened;
 //  - if a long B row is not in column order, every product of the segment is
 //    added with FP64 atomics into device memory: C's own values for FP64, a
 //    per-workgroup FP64 buffer for FP32 (rounded once on the copy out).  Only
 //    this workgroup touches those slots, so the atomics are workgroup-scoped.
+// Barriers are few (a row of one segment summed in one walk passes six): the
+// bitmap and the LDS accumulator are all zero between uses, each thread
+// clearing the words and slots it copies out, and the barriers of the next
+// publication order that clearing before the next walk.
+constexpr int kLongPos = 3840;        // chunk-boundary positions kept in LDS (boundaries x A entries)
+constexpr int kLongNumBlock = 512;    // A entries staged per block (the rows of this pass have few)
+
 template <typename T, typename IdxT, typename IdxC>
 __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
                                                              const NumArgs<T, IdxT, IdxC>* __restrict__ P,
                                                              BatchMap bm) {
-    constexpr int NT = kLongNumThreads, NW = kLongNumWaves;
+    constexpr int NT = kLongNumThreads, NW = kLongNumWaves, NB = kLongNumBlock;
     __shared__ uint32_t s_bits[kLongSegWords];
-    __shared__ uint32_t s_pfx[kLongSegWords];
+    __shared__ uint32_t s_pfx[kLongSegWords];        // set bits of the segment before each word
     __shared__ double s_vals[kLongVals];
-    __shared__ FlatStage<NT, true> s_st;
-    __shared__ long long s_red[NW];
+    __shared__ FlatStage<NB, true> s_st;
+    __shared__ int32_t s_pos[kLongPos];              // [chunk boundary][A entry]: position in the entry's B row
+    __shared__ long long s_pub[NW];                  // partials of the publications
+    __shared__ long long s_scan[NW];                 // partials of the prefix counts
     __shared__ int s_bound[kLongMaxChunks + 1];
-    __shared__ int s_next;
+    __shared__ int s_next[2];
 
     const int w = threadIdx.x / kWave;
     const int nL = (int)*bm.n_long;
-    for (;;) {
-        if (threadIdx.x == 0) s_next = (int)atomicAdd(&bm.queue[1], 1u);
-        __syncthreads();
-        const int j = uniform_i32(s_next);
+    for (int x = threadIdx.x; x < kLongSegWords; x += NT) s_bits[x] = 0u;
+    for (int x = threadIdx.x; x < kLongVals; x += NT) s_vals[x] = 0.0;
+    if (threadIdx.x == 0) s_next[0] = (int)atomicAdd(&bm.queue[1], 1u);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int j = uniform_i32(s_next[it & 1]);
         if (j >= nL) break;
+        // the next row's queue entry, taken now (see k_long_sym)
+        if (threadIdx.x == 0) s_next[(it + 1) & 1] = (int)atomicAdd(&bm.queue[1], 1u);
         const int2 ent = bm.long_list[j];
         const NumArgs<T, IdxT, IdxC> p = P ? P[uniform_i32(ent.x)] : p0;
         const int seg_cols = uniform_i32(p.th.group_lds_span);
@@ -366,7 +427,7 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
         const int64_t i = uniform_i32(ent.y);
         const IdxT rs = uniform(p.a_rp[i]);
         const int64_t nA = uniform((int64_t)p.a_rp[i + 1]) - (int64_t)rs;
-        const int nblk = (int)((nA + NT - 1) / NT);
+        const int nblk = (int)((nA + NB - 1) / NB);
         const int2 wn = p.win[i];
         const int lo = uniform_i32(wn.x);
         const int64_t span = uniform_i32(wn.y);
@@ -378,21 +439,24 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
         LongEnt en1{0, 0, 0.0};
         int64_t tot1 = 0;
         bool full1 = false;
-        if (nblk == 1) en1 = long_entry<NT, T, IdxT, true>(rs, nA, 0, p.a_col, p.a_val, p.b_rp);
+        if (nblk == 1) en1 = long_entry<NB, T, IdxT, true>(rs, nA, 0, p.a_col, p.a_val, p.b_rp);
         auto walk_all = [&](auto vals_tag, auto&& fn) {
             constexpr bool VL = decltype(vals_tag)::value;
             if (nblk == 1) {
                 if (!full1) {
-                    tot1 = flat_publish<NT, true>(s_st, en1.b0, en1.len, en1.a, s_red);
+                    tot1 = flat_publish<NT, NB, true>(s_st, en1.b0, en1.len, en1.a, s_pub);
                     full1 = true;
                 }
-                flat_walk<NT, T, VL, true, false>(s_st, tot1, p.b_col, p.b_val, w, NW, fn);
+                flat_walk<VL ? kFlatU : kFlatUCols, NB, T, VL, true, false>(s_st, (int)nA, tot1, p.b_col, p.b_val, w,
+                                                                            NW, fn);
                 return;
             }
             for (int b = 0; b < nblk; ++b) {
-                const LongEnt en = long_entry<NT, T, IdxT, true>(rs, nA, b, p.a_col, p.a_val, p.b_rp);
-                const int64_t tot = flat_publish<NT, true>(s_st, en.b0, en.len, en.a, s_red);
-                flat_walk<NT, T, VL, true, false>(s_st, tot, p.b_col, p.b_val, w, NW, fn);
+                const LongEnt en = long_entry<NB, T, IdxT, true>(rs, nA, b, p.a_col, p.a_val, p.b_rp);
+                const int64_t tot = flat_publish<NT, NB, true>(s_st, en.b0, en.len, en.a, s_pub);
+                const int ne = (int)min((int64_t)NB, nA - (int64_t)b * NB);
+                flat_walk<VL ? kFlatU : kFlatUCols, NB, T, VL, true, false>(s_st, ne, tot, p.b_col, p.b_val, w, NW,
+                                                                            fn);
             }
         };
         using NoVals = std::integral_constant<bool, false>;
@@ -400,11 +464,11 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
 
         int64_t off = 0;
         for (int64_t s0 = 0; s0 < span; s0 += seg_cols) {
+            // a row's first walk follows a publication; a later segment's may not
+            if (s0 > 0) __syncthreads();
             const int seg_lo = lo + (int)s0;
             const int seg_w = (int)((min((int64_t)seg_cols, span - s0) + 31) >> 5);
             const int seg_hi = seg_lo + seg_w * 32;
-            for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
-            __syncthreads();
             walk_all(NoVals{}, [&](int col, double) {
                 if (col >= seg_lo && col < seg_hi) {
                     const int d = col - seg_lo;
@@ -412,22 +476,28 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 }
             });
             __syncthreads();
-            // thread t owns words [t*per, t*per + per)
+            // thread t owns words [w0, w1), w0 = t * per
             const int per = (seg_w + NT - 1) / NT;
             const int w0 = min((int)threadIdx.x * per, seg_w), w1 = min(w0 + per, seg_w);
             long long local = 0;
             for (int x = w0; x < w1; ++x) local += __popc(s_bits[x]);
             long long seg_nnz_ll;
-            long long run = block_excl_scan_i64<NT>(local, s_red, &seg_nnz_ll);
-            for (int x = w0; x < w1; ++x) {
-                s_pfx[x] = (uint32_t)run;
-                run += __popc(s_bits[x]);
+            const int rank0 = (int)block_excl_scan1_i64<NT>(local, s_scan, &seg_nnz_ll);   // this thread's first rank
+            {
+                int run = rank0;
+                for (int x = w0; x < w1; ++x) {
+                    s_pfx[x] = (uint32_t)run;
+                    run += __popc(s_bits[x]);
+                }
             }
             if (off + seg_nnz_ll > nc_row) {  // pattern differs from the symbolic pass
                 if (threadIdx.x == 0) atomicOr(&p.ctr->bad_csr, 4u);
+                __syncthreads();
+                for (int x = threadIdx.x; x < seg_w; x += NT) s_bits[x] = 0u;
                 break;
             }
             const int seg_nnz = (int)seg_nnz_ll;
+            __syncthreads();   // prefix counts complete
             auto rank_of = [&](int col) {
                 const int d = col - seg_lo;
                 const int x = d >> 5;
@@ -436,14 +506,15 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
             if (threadIdx.x == 0)
                 atomicAdd(seg_nnz <= V ? &p.ctr->seg_lds : (sorted_b ? &p.ctr->seg_chunked : &p.ctr->seg_device), 1u);
             if (seg_nnz <= V) {
-                // the whole segment in LDS
-                for (int x = threadIdx.x; x < seg_nnz; x += NT) s_vals[x] = 0.0;
-                __syncthreads();
+                // the whole segment in LDS (the accumulator is zero)
                 walk_all(Vals{}, [&](int col, double v) {
                     if (col >= seg_lo && col < seg_hi) atomicAdd(&s_vals[rank_of(col)], v);
                 });
                 __syncthreads();
-                for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)s_vals[x];
+                for (int x = threadIdx.x; x < seg_nnz; x += NT) {
+                    p.c_val[cb + off + x] = (T)s_vals[x];
+                    s_vals[x] = 0.0;
+                }
             } else if (sorted_b) {
                 // rank chunks, each summed in LDS and written to C as it completes
                 const int nch = (seg_nnz + V - 1) / V;
@@ -453,41 +524,64 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                     s_bound[0] = seg_lo;
                     s_bound[nch] = seg_hi;
                 }
-                for (int x = w0; x < w1; ++x) {
-                    const int r0 = (int)s_pfx[x];
-                    const uint32_t bw = s_bits[x];
-                    const int c = __popc(bw);
-                    // every multiple of V in [r0, r0 + c) but 0
-                    for (int k = max(1, (r0 + V - 1) / V); k * V < r0 + c; ++k) {
-                        uint32_t m = bw;
-                        for (int t = k * V - r0; t > 0; --t) m &= m - 1;  // drop the lower set bits
-                        s_bound[k] = seg_lo + x * 32 + (__ffs(m) - 1);
+                {
+                    int r = rank0;
+                    for (int x = w0; x < w1; ++x) {
+                        const int r0 = r;
+                        const uint32_t bw = s_bits[x];
+                        const int c = __popc(bw);
+                        // every multiple of V in [r0, r0 + c) but 0
+                        for (int k = max(1, (r0 + V - 1) / V); k * V < r0 + c; ++k) {
+                            uint32_t m = bw;
+                            for (int t = k * V - r0; t > 0; --t) m &= m - 1;  // drop the lower set bits
+                            s_bound[k] = seg_lo + x * 32 + (__ffs(m) - 1);
+                        }
+                        r += c;
                     }
                 }
                 __syncthreads();
-                // with one block, each thread's position in its B row carries
-                // from one chunk to the next (the chunk's range starts there)
-                int64_t cur1 = 0;
+                // positions of every boundary in every B row, all searches side
+                // by side (one block of entries, and room for them in LDS)
+                const int ne1 = (int)nA;
+                const bool pos_lds = nblk == 1 && (int64_t)(nch + 1) * ne1 <= kLongPos;
+                if (pos_lds) {
+                    for (int x = threadIdx.x; x < (nch + 1) * ne1; x += NT) {
+                        const int c = x / ne1, e = x - c * ne1;
+                        const int64_t eb0 = s_st.qs[e];   // the full publication (the bitmap walk's)
+                        const int64_t elen = s_st.pre[e + 1] - s_st.pre[e];
+                        s_pos[x] = (int32_t)lower_col(p.b_col + eb0, 0, elen, s_bound[c]);
+                    }
+                    __syncthreads();
+                }
                 for (int c = 0; c < nch; ++c) {
-                    const int clo = s_bound[c], chi = s_bound[c + 1];
                     const int r0 = c * V, rn = min(V, seg_nnz - r0);
-                    for (int x = threadIdx.x; x < rn; x += NT) s_vals[x] = 0.0;
                     auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
                     for (int b = 0; b < nblk; ++b) {
-                        const LongEnt en = nblk == 1 ? en1 : long_entry<NT, T, IdxT, true>(rs, nA, b, p.a_col,
+                        const LongEnt en = nblk == 1 ? en1 : long_entry<NB, T, IdxT, true>(rs, nA, b, p.a_col,
                                                                                            p.a_val, p.b_rp);
-                        const int32_t* brow = p.b_col + en.b0;
-                        const int64_t qlo = (nblk == 1 && c > 0) ? cur1 : lower_col(brow, 0, en.len, clo);
-                        const int64_t qhi = lower_col(brow, qlo, en.len, chi);
-                        cur1 = qhi;
-                        // publishing (its barriers) also orders the zeroing above before the adds
-                        const int64_t tot = flat_publish<NT, true>(s_st, en.b0 + qlo, qhi - qlo, en.a, s_red);
-                        flat_walk<NT, T, true, true, false>(s_st, tot, p.b_col, p.b_val, w, NW, add);
+                        int64_t qlo = 0, qhi = 0;
+                        if (pos_lds) {
+                            if ((int)threadIdx.x < ne1) {
+                                qlo = s_pos[c * ne1 + threadIdx.x];
+                                qhi = s_pos[(c + 1) * ne1 + threadIdx.x];
+                            }
+                        } else {
+                            const int32_t* brow = p.b_col + en.b0;
+                            qlo = lower_col(brow, 0, en.len, s_bound[c]);
+                            qhi = lower_col(brow, qlo, en.len, s_bound[c + 1]);
+                        }
+                        // the publication's barriers also order the previous chunk's
+                        // copy-out (and clearing) before this chunk's adds
+                        const int64_t tot = flat_publish<NT, NB, true>(s_st, en.b0 + qlo, qhi - qlo, en.a, s_pub);
+                        const int ne = (int)min((int64_t)NB, nA - (int64_t)b * NB);
+                        flat_walk<kFlatU, NB, T, true, true, false>(s_st, ne, tot, p.b_col, p.b_val, w, NW, add);
                     }
                     full1 = false;
                     __syncthreads();
-                    for (int x = threadIdx.x; x < rn; x += NT) p.c_val[cb + off + r0 + x] = (T)s_vals[x];
-                    __syncthreads();
+                    for (int x = threadIdx.x; x < rn; x += NT) {
+                        p.c_val[cb + off + r0 + x] = (T)s_vals[x];
+                        s_vals[x] = 0.0;
+                    }
                 }
             } else {
                 // a long B row out of column order: every product into device memory
@@ -504,19 +598,23 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                     if (col >= seg_lo && col < seg_hi)
                         __hip_atomic_fetch_add(&acc[rank_of(col)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 });
-                if constexpr (sizeof(T) != sizeof(double)) {
-                    // the adds of every wavefront are complete before the buffer is read
-                    // back (all of the workgroup's accesses go through one CU, so a
-                    // workgroup-scope fence is enough: an agent-scope one would write
-                    // back and invalidate the whole L2 of the XCD, per row)
-                    __threadfence_block();
-                    __syncthreads();
+                // the adds of every wavefront are complete (and their rank reads
+                // done) before the buffer is read back and the bitmap cleared
+                // (all of the workgroup's accesses go through one CU, so a
+                // workgroup-scope fence is enough: an agent-scope one would write
+                // back and invalidate the whole L2 of the XCD, per row)
+                __threadfence_block();
+                __syncthreads();
+                if constexpr (sizeof(T) != sizeof(double))
                     for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)acc[x];
-                }
             }
-            for (int x = w0; x < w1; ++x) {
+            // columns in ascending order, thread t taking words t, t + NT, ...
+            // (neighbouring threads write neighbouring entries); the words are
+            // cleared for the next segment or row
+            for (int x = threadIdx.x; x < seg_w; x += NT) {
                 uint32_t bw = s_bits[x];
                 int64_t o = cb + off + s_pfx[x];
+                s_bits[x] = 0u;
                 while (bw) {
                     const int b = __ffs(bw) - 1;
                     bw &= bw - 1;
@@ -524,8 +622,10 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 }
             }
             off += seg_nnz;
-            __syncthreads();
         }
+        // a row without segments (no partial product) passed no barrier since
+        // the next row's queue slot was written
+        if (span <= 0) __syncthreads();
     }
 }
 
