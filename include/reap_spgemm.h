@@ -122,6 +122,15 @@ typedef struct {
  *                        per-product spine over the tile sums, then the
  *                        rows).  <= 1024; 0 = default 1024; negative: always
  *                        two launches.
+ *   mid_values        -- long rows with at most this many entries of C whose
+ *                        columns span at most 65536 columns are summed by
+ *                        medium workgroups (256 threads, three per CU)
+ *                        instead of one 1024-thread workgroup per CU
+ *                        (<= 2048; 0 = default 2048; negative: none).
+ *   long_sym_narrow   -- the symbolic long-row pass runs 256-thread
+ *                        workgroups with a 65536-column bitmap (twice as
+ *                        many per CU) when every product of the call has at
+ *                        most 65536 columns: 0 = yes (default), negative = no.
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -137,7 +146,9 @@ typedef struct {
     int32_t long_workgroups_per_cu;
     int32_t test_fail_alloc;
     int32_t scan_onepass_tiles;
-    int32_t reserved[4];
+    int32_t mid_values;
+    int32_t long_sym_narrow;
+    int32_t reserved[2];
 } reap_options_t;
 
 /*
@@ -155,6 +166,7 @@ typedef struct {
     int64_t long_segments_lds;      /* long-row window segments summed in LDS in one walk */
     int64_t long_segments_chunked;  /* ... summed in LDS rank chunks (B rows in column order) */
     int64_t long_segments_device;   /* ... summed with device-memory atomics */
+    int64_t group_medium; /* long rows summed by medium workgroups (of `group`) */
 } reap_bin_stats_t;
 
 /*

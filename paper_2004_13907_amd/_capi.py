@@ -68,7 +68,9 @@ class reap_options_t(ctypes.Structure):
         ("long_workgroups_per_cu", ctypes.c_int32),
         ("test_fail_alloc", ctypes.c_int32),
         ("scan_onepass_tiles", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("mid_values", ctypes.c_int32),
+        ("long_sym_narrow", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -83,6 +85,7 @@ class reap_bin_stats_t(ctypes.Structure):
         ("long_segments_lds", ctypes.c_int64),
         ("long_segments_chunked", ctypes.c_int64),
         ("long_segments_device", ctypes.c_int64),
+        ("group_medium", ctypes.c_int64),
     ]
 
 

@@ -34,14 +34,35 @@
 
 namespace reap {
 
-constexpr int kLongThreads = 512;       // symbolic pass
-constexpr int kLongWaves = kLongThreads / kWave;
-constexpr int kLongNumThreads = 1024;   // numeric pass (one workgroup per CU: its LDS is ~156 KB)
-constexpr int kLongNumWaves = kLongNumThreads / kWave;
-constexpr int kLongSegWords = 8192;     // 262144 columns per window segment
-constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS
+constexpr int kLongSegWords = 8192;     // 262144 columns per window segment (the wide shapes)
+constexpr int kLongVals = 8192;         // numeric: FP64 accumulator slots in LDS (the large shape)
 constexpr int kLongMinVals = 256;       // smallest rank chunk accepted
-constexpr int kLongMaxChunks = kLongSegWords * 32 / kLongMinVals;
+
+// Workgroup shapes.  Symbolic: threads and bitmap words per segment.  The
+// narrow one serves batches whose products all have at most 65536 columns.
+struct LongSymWide {
+    static constexpr int NT = 512, SEGW = kLongSegWords;   // two workgroups per CU
+};
+struct LongSymNarrow {
+    static constexpr int NT = 256, SEGW = 2048;            // four per CU
+};
+// Numeric: threads, bitmap words per segment, LDS accumulator slots, A
+// entries staged per block, chunk-boundary positions kept in LDS, and which
+// part of the split list it takes.  Large rows: one workgroup per CU (its
+// LDS is ~159 KB).  Medium rows -- a window of at most 65536 columns and at
+// most 2048 entries of C, the size of most rows of the uniform-random
+// products -- take a quarter of the threads and ~43 KB of LDS, three
+// workgroups per CU.
+struct LongNumLarge {
+    static constexpr int NT = 1024, SEGW = kLongSegWords, VMAX = kLongVals, NB = 512, POS = 3840;
+    static constexpr bool MID = false;
+};
+struct LongNumMid {
+    static constexpr int NT = 256, SEGW = 2048, VMAX = 2048, NB = 256, POS = 1024;
+    static constexpr bool MID = true;
+};
+constexpr int kMidCols = LongNumMid::SEGW * 32;   // widest window of a medium row
+constexpr int kMidPerCu = 3;                      // medium workgroups per CU
 constexpr int kFlatU = 4;               // products per lane and step of a flattened walk that reads values
 constexpr int kFlatUCols = 8;           // ... of one that reads columns only
 constexpr unsigned kUnsortedB = 8u;     // Counters::bad_csr bit: a B row read by a long row is not in column order
@@ -218,11 +239,11 @@ __device__ __forceinline__ long long long_row_count(IdxT rs, int64_t nA, const i
 // [min column, max column] (one extra walk of the products).  The segment
 // bitmap is all zero between segments: its words are cleared as they are
 // counted.
-template <typename IdxT>
-__global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P,
-                                                          BatchMap bm) {
-    constexpr int NT = kLongThreads, NW = kLongWaves;
-    __shared__ uint32_t s_bits[kLongSegWords];
+template <typename IdxT, typename S>
+__global__ void __launch_bounds__(S::NT) k_long_sym(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P,
+                                                   BatchMap bm) {
+    constexpr int NT = S::NT, NW = NT / kWave;
+    __shared__ uint32_t s_bits[S::SEGW];
     __shared__ FlatStage<NT, false> s_st;
     __shared__ long long s_pub[NW];      // partials of the publications
     __shared__ long long s_red[NW];      // partials of the other reductions
@@ -235,7 +256,7 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
     const int lane = lane_id();
     const int nL = (int)*bm.n_long;
     if (nL == 0) return;   // the usual case on regular inputs: leave before touching the queue
-    for (int x = threadIdx.x; x < kLongSegWords; x += NT) s_bits[x] = 0u;
+    for (int x = threadIdx.x; x < S::SEGW; x += NT) s_bits[x] = 0u;
     if (threadIdx.x == 0) s_next[0] = (int)atomicAdd(&bm.queue[0], 1u);
     __syncthreads();
     for (int it = 0;; ++it) {
@@ -247,7 +268,7 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
         if (threadIdx.x == 0) s_next[(it + 1) & 1] = (int)atomicAdd(&bm.queue[0], 1u);
         const int2 ent = bm.long_list[j];
         const SymArgs<IdxT> p = P ? P[uniform_i32(ent.x)] : p0;
-        const int seg_cols = uniform_i32(p.th.group_lds_span);
+        const int seg_cols = min(uniform_i32(p.th.group_lds_span), S::SEGW * 32);
         const int64_t i = uniform_i32(ent.y);
         const IdxT rs = uniform(p.a_rp[i]);
         const int64_t nA = uniform((int64_t)p.a_rp[i + 1]) - (int64_t)rs;
@@ -361,6 +382,17 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
             atomicMax(&p.ctr->max_prod, (unsigned)min(prods, (long long)UINT32_MAX));
             atomicMax(&p.ctr->max_nnz, (unsigned)nnz);
             atomicMax(&p.ctr->max_group_nnz, (unsigned)nnz);
+            // the numeric pass takes medium and large rows in workgroups of
+            // their own shape; rows without an entry of C need no numeric work
+            if (nnz > 0) {
+                if (nnz <= p.th.mid_nnz && span <= kMidCols) {
+                    const unsigned k = atomicAdd(&bm.n_split[0], 1u);
+                    bm.split_list[k] = ent;
+                } else {
+                    const unsigned k = atomicAdd(&bm.n_split[1], 1u);
+                    bm.split_list[bm.split_cap - 1u - k] = ent;
+                }
+            }
         }
         // s_cnt, s_cmin, s_cmax are read again only after the next row's
         // publication and walk (two barriers on)
@@ -368,13 +400,14 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 }
 
 // ---------------------------------------------------------------------------
-// Numeric pass for the long-row list, one workgroup of 1024 threads per row.
-// Per segment of the row's window (up to 262144 columns): (1) bitmap of the
+// Numeric pass for one part of the split list, one workgroup of shape S per
+// row (1024 threads for large rows, 256 for medium ones).
+// Per segment of the row's window (up to S::SEGW * 32 columns): (1) bitmap of the
 // segment's columns, (2) prefix count of set bits per word (block scan), so
 // the rank of a column -- its position in the sorted row -- is one LDS read
 // and a popcount, (3) accumulation by rank, (4) columns written from the
 // bitmap in ascending order.  Accumulation:
-//  - a segment with at most V = group_lds_values (<= 8192) entries is summed
+//  - a segment with at most V = group_lds_values (<= S::VMAX) entries is summed
 //    in LDS in one flattened walk of the products;
 //  - a larger segment is cut into nch chunks of V consecutive ranks (a column
 //    range each).  If the long B rows are in column order (checked by the
@@ -390,39 +423,40 @@ __global__ void __launch_bounds__(kLongThreads) k_long_sym(SymArgs<IdxT> p0, con
 // bitmap and the LDS accumulator are all zero between uses, each thread
 // clearing the words and slots it copies out, and the barriers of the next
 // publication order that clearing before the next walk.
-constexpr int kLongPos = 3840;        // chunk-boundary positions kept in LDS (boundaries x A entries)
-constexpr int kLongNumBlock = 512;    // A entries staged per block (the rows of this pass have few)
-
-template <typename T, typename IdxT, typename IdxC>
-__global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, IdxC> p0,
-                                                             const NumArgs<T, IdxT, IdxC>* __restrict__ P,
-                                                             BatchMap bm) {
-    constexpr int NT = kLongNumThreads, NW = kLongNumWaves, NB = kLongNumBlock;
-    __shared__ uint32_t s_bits[kLongSegWords];
-    __shared__ uint32_t s_pfx[kLongSegWords];        // set bits of the segment before each word
-    __shared__ double s_vals[kLongVals];
+template <typename T, typename IdxT, typename IdxC, typename S>
+__global__ void __launch_bounds__(S::NT) k_long_num(NumArgs<T, IdxT, IdxC> p0,
+                                                   const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm) {
+    constexpr int NT = S::NT, NW = NT / kWave, NB = S::NB;
+    constexpr int kMaxChunks = S::SEGW * 32 / kLongMinVals;
+    __shared__ uint32_t s_bits[S::SEGW];
+    __shared__ uint32_t s_pfx[S::SEGW];              // set bits of the segment before each word
+    __shared__ double s_vals[S::VMAX];
     __shared__ FlatStage<NB, true> s_st;
-    __shared__ int32_t s_pos[kLongPos];              // [chunk boundary][A entry]: position in the entry's B row
+    __shared__ int32_t s_pos[S::POS];                // [chunk boundary][A entry]: position in the entry's B row
     __shared__ long long s_pub[NW];                  // partials of the publications
     __shared__ long long s_scan[NW];                 // partials of the prefix counts
-    __shared__ int s_bound[kLongMaxChunks + 1];
+    __shared__ int s_bound[kMaxChunks + 1];
     __shared__ int s_next[2];
 
     const int w = threadIdx.x / kWave;
-    const int nL = (int)*bm.n_long;
-    for (int x = threadIdx.x; x < kLongSegWords; x += NT) s_bits[x] = 0u;
-    for (int x = threadIdx.x; x < kLongVals; x += NT) s_vals[x] = 0.0;
-    if (threadIdx.x == 0) s_next[0] = (int)atomicAdd(&bm.queue[1], 1u);
+    const int nL = (int)bm.n_split[S::MID ? 0 : 1];
+    if (nL == 0) return;
+    unsigned int* const queue = &bm.queue[S::MID ? 2 : 1];
+    // medium rows from the start of the split list, large ones from its end
+    auto entry = [&](int jj) { return bm.split_list[S::MID ? (unsigned)jj : bm.split_cap - 1u - (unsigned)jj]; };
+    for (int x = threadIdx.x; x < S::SEGW; x += NT) s_bits[x] = 0u;
+    for (int x = threadIdx.x; x < S::VMAX; x += NT) s_vals[x] = 0.0;
+    if (threadIdx.x == 0) s_next[0] = (int)atomicAdd(queue, 1u);
     __syncthreads();
     for (int it = 0;; ++it) {
         const int j = uniform_i32(s_next[it & 1]);
         if (j >= nL) break;
         // the next row's queue entry, taken now (see k_long_sym)
-        if (threadIdx.x == 0) s_next[(it + 1) & 1] = (int)atomicAdd(&bm.queue[1], 1u);
-        const int2 ent = bm.long_list[j];
+        if (threadIdx.x == 0) s_next[(it + 1) & 1] = (int)atomicAdd(queue, 1u);
+        const int2 ent = entry(j);
         const NumArgs<T, IdxT, IdxC> p = P ? P[uniform_i32(ent.x)] : p0;
-        const int seg_cols = uniform_i32(p.th.group_lds_span);
-        const int V = min(max(uniform_i32(p.th.group_lds_values), kLongMinVals), kLongVals);
+        const int seg_cols = min(uniform_i32(p.th.group_lds_span), S::SEGW * 32);
+        const int V = min(max(uniform_i32(p.th.group_lds_values), kLongMinVals), S::VMAX);
         const bool sorted_b = (uniform_i32((int)p.ctr->bad_csr) & kUnsortedB) == 0u;
         const int64_t i = uniform_i32(ent.y);
         const IdxT rs = uniform(p.a_rp[i]);
@@ -543,7 +577,7 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
                 // positions of every boundary in every B row, all searches side
                 // by side (one block of entries, and room for them in LDS)
                 const int ne1 = (int)nA;
-                const bool pos_lds = nblk == 1 && (int64_t)(nch + 1) * ne1 <= kLongPos;
+                const bool pos_lds = nblk == 1 && (int64_t)(nch + 1) * ne1 <= S::POS;
                 if (pos_lds) {
                     for (int x = threadIdx.x; x < (nch + 1) * ne1; x += NT) {
                         const int c = x / ne1, e = x - c * ne1;
@@ -629,10 +663,10 @@ __global__ void __launch_bounds__(kLongNumThreads) k_long_num(NumArgs<T, IdxT, I
     }
 }
 
-// Rewinds the numeric pass's long-row counter (a kernel, so that the
-// sequence can be captured in a graph).
+// Rewinds the numeric pass's queue counters (a kernel, so that the sequence
+// can be captured in a graph).
 __global__ void k_long_rewind(unsigned int* queue) {
-    if (threadIdx.x == 0) queue[1] = 0u;
+    if (threadIdx.x < 2) queue[1 + threadIdx.x] = 0u;
 }
 
 }  // namespace reap

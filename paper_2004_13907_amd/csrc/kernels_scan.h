@@ -18,10 +18,17 @@ struct ScanArgs {
     Counters* ctr;
     void* c_rp;            // [m + 1] C row pointer (IdxC)
     Counters* h_ctr;       // the product's counters in pinned host memory (device-mapped), or null
-    const unsigned int* n_long;   // long-row count of the batch ...
-    unsigned int* h_nlong;        // ... and its host copy (written by product 0), or null
+    const unsigned int* n_long;   // long-row counter block of the batch ...
+    unsigned int* h_nlong;        // ... and the host copy of its counts (written by product 0), or null
     TileStat* h_tiles;     // [ntiles] the product's tile statistics in pinned host memory (one-launch scan)
 };
+
+// Host copy of the long-row counts: all long rows, medium rows, large rows.
+__device__ __forceinline__ void copy_long_counts(unsigned int* h, const unsigned int* n_long) {
+    h[0] = n_long[kLongCtrCount];
+    h[1] = n_long[kLongCtrSplit];
+    h[2] = n_long[kLongCtrSplit + 1];
+}
 
 // Tile t of product q: tile_start[q] <= blockIdx.x < tile_start[q + 1].
 struct ScanMap {
@@ -120,7 +127,7 @@ __global__ void __launch_bounds__(1024) k_scan_spine(ScanArgs s0, const ScanArgs
         // the host reads the counters straight from its pinned mirror once
         // the stream is synchronised (no device-to-host copy is enqueued)
         if (sa.h_ctr) *sa.h_ctr = *ctr;
-        if (sa.h_nlong && blockIdx.x == 0) *sa.h_nlong = *sa.n_long;
+        if (sa.h_nlong && blockIdx.x == 0) copy_long_counts(sa.h_nlong, sa.n_long);
         __threadfence_system();
     }
 }
@@ -178,7 +185,7 @@ k_scan_onepass(ScanArgs s0, const ScanArgs* __restrict__ S, ScanMap sm, int tota
             const ScanArgs& sa = S ? S[q] : s0;
             if (sa.m == 0) static_cast<IdxC*>(sa.c_rp)[0] = (IdxC)0;
         }
-        if (threadIdx.x == 0) *s0.h_nlong = *s0.n_long;
+        if (threadIdx.x == 0) copy_long_counts(s0.h_nlong, s0.n_long);
         return;
     }
     ScanArgs sa;
@@ -252,7 +259,7 @@ __global__ void k_zero_counters(Counters* ctr, int nprod, unsigned int* n_long, 
     const int64_t x0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t x = x0; x < words; x += stride) p[x] = 0u;
     for (int64_t x = x0; x < ntiles; x += stride) tiles[x] = 0;
-    if (blockIdx.x == 0 && threadIdx.x < 3) n_long[threadIdx.x] = 0u;  // count and the two queue counters
+    if (blockIdx.x == 0 && threadIdx.x < kLongCtrWords) n_long[threadIdx.x] = 0u;  // counts and queue counters
 }
 
 }  // namespace reap

@@ -100,6 +100,7 @@ struct reap_spgemm_s {
     bool use_graph = false;   // capture each pass into a HIP graph, replay while the shape repeats
     bool debug_sync = false;  // REAP_DEBUG_SYNC=1: synchronise and log after every kernel
     int long_wg_per_cu = 2;   // workgroups per CU walking the long-row list
+    bool sym_narrow = true;   // narrow symbolic long-row workgroups when every product has <= 65536 columns
     int fail_alloc_at = 0;    // test hook: the n-th device allocation of the plan fails (0 = never)
     int scan_onepass = kScanOnePassTiles;  // most tiles per product for the one-launch scan
     int alloc_count = 0;      // device allocations attempted by the plan
@@ -121,6 +122,7 @@ struct reap_spgemm_s {
     int32_t* rnnz = nullptr;
     int2* win = nullptr;
     int2* long_list = nullptr;
+    int2* split_list = nullptr;    // long rows sorted into medium (from the start) and large (from the end)
     WGPart* parts = nullptr;       // per wavefront-kernel workgroup (all products)
     long long* tiles = nullptr;    // per scan tile (all products)
     int32_t* blk_start = nullptr;  // [nprod + 1]
@@ -153,7 +155,9 @@ struct reap_spgemm_s {
     int32_t total_blocks = 0, total_tiles = 0;
     int32_t max_prod_tiles = 0;     // most scan tiles of one product in the batch
     unsigned int long_rows = 0;
-    int long_grid = 1;
+    unsigned int mid_rows = 0, big_rows = 0;   // the split of the long rows (numeric shapes)
+    int mid_grid = 1, big_grid = 1;
+    int long_grid = 1;             // the wider of the two grids (FP64 accumulator slots)
     int64_t gvals_stride = 0;
     Counters agg{};                // summed / maxed over the products (bin statistics)
 
@@ -224,7 +228,8 @@ hipError_t dev_malloc(reap_spgemm_s* p, void** ptr, size_t bytes) {
 // Offsets of the workspace slices for R rows, Bk wavefront-kernel
 // workgroups, Tl scan tiles and Q products (256-byte aligned).
 struct WsLayout {
-    size_t o_ctr, o_nlong, o_cls, o_rnnz, o_win, o_long, o_parts, o_tiles, o_bs, o_ts, o_sa, o_na, o_sc, total;
+    size_t o_ctr, o_nlong, o_cls, o_rnnz, o_win, o_long, o_split, o_parts, o_tiles, o_bs, o_ts, o_sa, o_na, o_sc,
+        total;
 };
 
 WsLayout ws_layout(int64_t R, int32_t Bk, int32_t Tl, int64_t Q) {
@@ -236,11 +241,12 @@ WsLayout ws_layout(int64_t R, int32_t Bk, int32_t Tl, int64_t Q) {
         return o;
     };
     L.o_ctr = carve((size_t)Q * sizeof(Counters));
-    L.o_nlong = carve(4 * sizeof(unsigned int));  // long-row count, two queue counters
+    L.o_nlong = carve(kLongCtrWords * sizeof(unsigned int));  // long-row counts and queue counters
     L.o_cls = carve((size_t)R);
     L.o_rnnz = carve((size_t)R * 4);
     L.o_win = carve((size_t)R * 8);
     L.o_long = carve((size_t)R * 8);
+    L.o_split = carve((size_t)R * 8);
     L.o_parts = carve((size_t)Bk * sizeof(WGPart));
     L.o_tiles = carve((size_t)Tl * 8);
     L.o_bs = carve((size_t)(Q + 1) * 4);
@@ -313,6 +319,7 @@ void bind_workspace(reap_spgemm_s* p, char* b, const WsLayout& L) {
     p->rnnz = reinterpret_cast<int32_t*>(b + L.o_rnnz);
     p->win = reinterpret_cast<int2*>(b + L.o_win);
     p->long_list = reinterpret_cast<int2*>(b + L.o_long);
+    p->split_list = reinterpret_cast<int2*>(b + L.o_split);
     p->parts = reinterpret_cast<WGPart*>(b + L.o_parts);
     p->tiles = reinterpret_cast<long long*>(b + L.o_tiles);
     p->blk_start = reinterpret_cast<int32_t*>(b + L.o_bs);
@@ -421,8 +428,11 @@ BatchMap batch_map(const reap_spgemm_s* p) {
     bm.blk_start = p->blk_start;
     bm.nprod = p->nprod;
     bm.long_list = p->long_list;
-    bm.n_long = p->n_long;
-    bm.queue = p->n_long + 1;
+    bm.n_long = p->n_long + kLongCtrCount;
+    bm.queue = p->n_long + kLongCtrQueue;
+    bm.split_list = p->split_list;
+    bm.split_cap = (unsigned int)std::max<int64_t>(p->total_rows, 1);
+    bm.n_split = p->n_long + kLongCtrSplit;
     return bm;
 }
 
@@ -527,10 +537,19 @@ reap_status_t launch_symbolic(reap_spgemm_s* p, const SymArgs<IdxT>& a0, const S
             hipLaunchKernelGGL((k_sym_wave<IdxT, false, false>), grid, block, 0, p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_sym_wave");
-        // the long-row count is known on the device only: a fixed grid takes rows from the list
-        const int lgrid =
-            (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * p->long_wg_per_cu));
-        hipLaunchKernelGGL(k_long_sym<IdxT>, dim3(lgrid), dim3(kLongThreads), 0, p->stream, a0, P, bm);
+        // the long-row count is known on the device only: a fixed grid takes rows
+        // from the list; narrow workgroups (twice as many) when every product has
+        // at most LongSymNarrow::SEGW * 32 columns
+        bool narrow = p->sym_narrow;
+        for (int q = 0; q < p->nprod && narrow; ++q) narrow = p->prods[(size_t)q].n <= LongSymNarrow::SEGW * 32;
+        const int per_cu = p->long_wg_per_cu * (narrow ? 2 : 1);
+        const int lgrid = (int)std::max<int64_t>(1, std::min<int64_t>(p->total_rows, (int64_t)p->num_cus * per_cu));
+        if (narrow)
+            hipLaunchKernelGGL((k_long_sym<IdxT, LongSymNarrow>), dim3(lgrid), dim3(LongSymNarrow::NT), 0, p->stream,
+                               a0, P, bm);
+        else
+            hipLaunchKernelGGL((k_long_sym<IdxT, LongSymWide>), dim3(lgrid), dim3(LongSymWide::NT), 0, p->stream, a0,
+                               P, bm);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_long_sym");
     }
@@ -739,9 +758,12 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     REAP_HIP(hipStreamSynchronize(p->stream));
     fold_events(p);  // this call's symbolic phases and the previous numeric call's phases
 
-    const unsigned int nl =
-        *reinterpret_cast<const unsigned int*>(reinterpret_cast<const char*>(p->h_ctr) + p->h_ctr_cap * sizeof(Counters));
+    const unsigned int* hl =
+        reinterpret_cast<const unsigned int*>(reinterpret_cast<const char*>(p->h_ctr) + p->h_ctr_cap * sizeof(Counters));
+    const unsigned int nl = hl[0];
     p->long_rows = nl;
+    p->mid_rows = hl[1];
+    p->big_rows = hl[2];
     p->agg = Counters{};
     unsigned int max_group_nnz = 0;
     bool overflow = false;
@@ -778,7 +800,9 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
     // out of column order (the rank-chunk walks need sorted rows)
     bool unsorted_long = false;
     for (int q = 0; q < p->nprod; ++q) unsorted_long |= (p->h_ctr[q].bad_csr & kUnsortedB) != 0u;
-    p->long_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)nl, (int64_t)p->num_cus));
+    p->mid_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->mid_rows, (int64_t)p->num_cus * kMidPerCu));
+    p->big_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)p->big_rows, (int64_t)p->num_cus));
+    p->long_grid = std::max(p->mid_grid, p->big_grid);
     p->gvals_stride = 0;
     p->gvals_ptr = nullptr;
     if (p->dtype == REAP_F32 && nl > 0 && unsorted_long) {
@@ -877,13 +901,21 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     }
     ev_record(p, kPhNumHash, true);
     ev_record(p, kPhNumGroup, false);
-    if (p->long_rows > 0) {
+    if (p->mid_rows + p->big_rows > 0) {
         hipLaunchKernelGGL(k_long_rewind, dim3(1), dim3(64), 0, p->stream, bm.queue);
         REAP_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC>), dim3(p->long_grid), dim3(kLongNumThreads), 0, p->stream, a0,
-                           P, bm);
+    }
+    if (p->mid_rows > 0) {
+        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC, LongNumMid>), dim3(p->mid_grid), dim3(LongNumMid::NT), 0,
+                           p->stream, a0, P, bm);
         REAP_LAUNCH_CHECK();
-        debug_step(p, "k_long_num");
+        debug_step(p, "k_long_num<mid>");
+    }
+    if (p->big_rows > 0) {
+        hipLaunchKernelGGL((k_long_num<T, IdxT, IdxC, LongNumLarge>), dim3(p->big_grid), dim3(LongNumLarge::NT), 0,
+                           p->stream, a0, P, bm);
+        REAP_LAUNCH_CHECK();
+        debug_step(p, "k_long_num<large>");
     }
     ev_record(p, kPhNumGroup, true);
     ev_record(p, kPhNumAll, true);
@@ -923,7 +955,8 @@ reap_status_t numeric_typed(reap_spgemm_s* p, const reap_csr_t* A, const reap_cs
     // this call allocates nothing either
     if (!p->use_graph || p->eager) return launch_numeric<T, IdxT, IdxC>(p, a0);
     std::vector<uint64_t> key = {p->ws_generation, (uint64_t)p->nprod, (uint64_t)p->total_blocks,
-                                 (uint64_t)p->long_rows, (uint64_t)p->long_grid,
+                                 (uint64_t)p->long_rows, (uint64_t)p->long_grid, (uint64_t)p->mid_rows,
+                                 (uint64_t)p->big_rows, (uint64_t)p->mid_grid, (uint64_t)p->big_grid,
                                  (uint64_t)(p->agg.cls[kClsWaveBmpS] > 0), (uint64_t)(p->agg.cls[kClsWaveHash] > 0),
                                  (uint64_t)sizeof(T), (uint64_t)sizeof(IdxT), (uint64_t)sizeof(IdxC),
                                  (uint64_t)(uintptr_t)p->gvals_ptr, (uint64_t)p->gvals_stride, (uint64_t)p->buf_b};
@@ -1135,6 +1168,8 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
     p->th.group_lds_values = clampi(o.group_lds_values, kLongMinVals, kLongVals, kLongVals);
     p->long_wg_per_cu = clampi(o.long_workgroups_per_cu, 1, 8, 2);
+    p->th.mid_nnz = clampi(o.mid_values, 0, LongNumMid::VMAX, LongNumMid::VMAX);
+    p->sym_narrow = o.long_sym_narrow >= 0;
     p->fail_alloc_at = std::max(0, o.test_fail_alloc);
     p->scan_onepass = clampi(o.scan_onepass_tiles, 0, kScanOnePassTiles, kScanOnePassTiles);
 
@@ -1261,6 +1296,7 @@ reap_status_t reap_spgemm_bin_stats(reap_spgemm_t p, reap_bin_stats_t* out) {
     out->wave_bitmap = (int64_t)(h.cls[kClsWaveBmpS] + h.cls[kClsWaveBmpL]);
     out->wave_hash = (int64_t)h.cls[kClsWaveHash];
     out->group = (int64_t)h.cls[kClsGroup];
+    out->group_medium = (int64_t)p->mid_rows;
     out->max_row_products = (int64_t)h.max_prod;
     out->max_row_nnz = (int64_t)h.max_nnz;
     out->long_segments_lds = out->long_segments_chunked = out->long_segments_device = 0;

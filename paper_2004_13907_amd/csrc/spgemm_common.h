@@ -97,13 +97,25 @@ static_assert(kScanTile % kRowsPerBlock == 0, "a wavefront workgroup's rows lie 
 // kernel serves product q with blk_start[q] <= b < blk_start[q + 1]; its
 // arguments are args[q] (or the kernel's by-value argument when nprod == 1).
 // Long rows of every product are appended to one list of (product, row).
+// The symbolic long-row pass sorts the list into medium rows (their window
+// and nnz(C_i) fit the medium numeric workgroup) and large rows: split_list
+// holds the medium ones from its start and the large ones from its end.
 struct BatchMap {
     const int32_t* blk_start;  // [nprod + 1]
     int32_t nprod;
     int2* long_list;           // [sum of rows]
     unsigned int* n_long;      // length of long_list
-    unsigned int* queue;       // next long_list entry to take: [0] symbolic, [1] numeric
+    unsigned int* queue;       // next entry to take: [0] long_list (symbolic), [1] large rows, [2] medium rows
+    int2* split_list;          // [split_cap]
+    unsigned int split_cap;
+    unsigned int* n_split;     // [0] medium rows, [1] large rows
 };
+
+// Layout of the plan's long-row counter block (unsigned ints).
+constexpr int kLongCtrCount = 0;     // long_list length
+constexpr int kLongCtrQueue = 1;     // three queue counters
+constexpr int kLongCtrSplit = 4;     // medium and large row counts
+constexpr int kLongCtrWords = 8;
 
 // Thresholds of one plan (clamped to the kernel capacities above).
 struct Thresholds {
@@ -113,6 +125,8 @@ struct Thresholds {
     int wave_small_nnz;      // <= kWaveSmallNnz
     int group_lds_span;      // <= 32 * kGroupBitsWords, multiple of 32
     int group_lds_values;    // FP64 LDS slots per rank chunk of a long row, kLongMinVals..kLongVals
+    int mid_nnz;             // long rows with at most this many entries of C (and a narrow window) are
+                             // medium rows; 0: none
 };
 
 }  // namespace reap

@@ -60,11 +60,35 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert lib.reap_spgemm_phase_times(None, None, 0) == _capi.REAP_ERR_INVALID_ARG
 
 
-def test_struct_layout_matches_header():
+def test_struct_layout_matches_header(tmp_path):
+    """Size and field offsets of every ctypes struct equal the C header's,
+    as compiled by the host C compiler."""
+    import shutil
+    import subprocess
     from paper_2004_13907_amd import _capi
-    assert ctypes.sizeof(_capi.reap_csr_t) == 8 * 3 + 8 + 8 * 3
-    assert ctypes.sizeof(_capi.reap_options_t) == 16 * 4
-    assert ctypes.sizeof(_capi.reap_bin_stats_t) == 9 * 8
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [_capi.reap_csr_t, _capi.reap_options_t, _capi.reap_bin_stats_t]
+    lines = ['#include "reap_spgemm.h"', "#include <stddef.h>", "#include <stdio.h>", "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (name, name))
+        for f, _ in st._fields_:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                      text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(st, f).offset, (name, f)
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

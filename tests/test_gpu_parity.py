@@ -120,7 +120,11 @@ def test_long_rows_uniform_random(reap, dtype):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     npdt = np.float64 if dtype == "f64" else np.float32
     A = synth.erdos_renyi(4000, 4000, 0.01, seed=31, dtype=npdt)
-    stats, _ = check_full(reap, A, A, dtype=tdt, label="uniform random 4000, d=0.01, %s" % dtype)
+    check_full(reap, A, A, dtype=tdt, label="uniform random 4000, d=0.01, %s" % dtype,
+               expect=lambda st: st["group_medium"] > 0.9 * st["group"])
+    check_full(reap, A, A, dtype=tdt, label="uniform random 4000, d=0.01, %s, no medium rows" % dtype,
+               mid_values=-1, long_sym_narrow=-1,
+               expect=lambda st: st["group"] > 0 and st["group_medium"] == 0)
 
 
 @HUNG_CASE
@@ -140,6 +144,8 @@ PATHS = {
     "group_segments_mixed": {"wave_max_products": 8, "group_lds_span": 96},
     "hash_tiny_wave": {"wave_max_span": 40, "wave_hash_products": 48, "wave_max_products": 200},
     "long_chunks": {"wave_max_products": -1, "group_lds_values": 256},
+    "long_large_only": {"wave_max_products": -1, "mid_values": -1, "long_sym_narrow": -1},
+    "long_chunks_large": {"wave_max_products": -1, "group_lds_values": 256, "mid_values": -1},
     "long_chunks_segments": {"wave_max_products": 8, "group_lds_span": 320, "group_lds_values": 256},
     "scan_two_launch": {"scan_onepass_tiles": -1},
 }
@@ -148,7 +154,9 @@ PATHS = {
 # long-row segments per accumulation method) on every input it is run on.
 PATH_EXPECT = {
     "default": lambda st: True,
-    "all_group": _all_long,
+    # every input here has at most 65536 columns and rows of C of at most 2048
+    # entries: the long rows are medium rows
+    "all_group": lambda st: _all_long(st) and st["group_medium"] == st["group"],
     "hash": lambda st: st["wave_bitmap"] == 0,
     "small_cap": lambda st: st["wave_bitmap"] == 0 and st["group"] > 0,
     "group_segments": lambda st: _all_long(st) and st["long_segments_lds"] + st["long_segments_chunked"]
@@ -157,6 +165,8 @@ PATH_EXPECT = {
     + st["long_segments_device"] >= st["group"],
     "hash_tiny_wave": lambda st: st["group"] > 0,
     "long_chunks": lambda st: _all_long(st),
+    "long_large_only": lambda st: _all_long(st) and st["group_medium"] == 0,
+    "long_chunks_large": lambda st: _all_long(st) and st["group_medium"] == 0,
     "long_chunks_segments": lambda st: st["group"] > 0,
     "scan_two_launch": lambda st: True,
 }
@@ -194,7 +204,8 @@ def test_forced_paths(reap, path, dtype):
                                densities=(0.01, 0.02) if seed == 3 else None)
         if seed == 1:
             # rows of C up to ~660 entries: 256 LDS slots must cut them into rank chunks
-            chunks = {"long_chunks": lambda st: st["long_segments_chunked"] > 0}.get(path, lambda st: True)
+            chunks = {"long_chunks": lambda st: st["long_segments_chunked"] > 0,
+                      "long_chunks_large": lambda st: st["long_segments_chunked"] > 0}.get(path, lambda st: True)
             want = lambda st: base(st) and chunks(st)  # noqa: E731
         else:
             want = lambda st: base(st) and irr(st)  # noqa: E731
