@@ -1,9 +1,16 @@
-"""Autotuner for batched products: times candidate launch parameters (bin
-thresholds, hash-table admission, long-row column segment, workgroups per CU
-of the long-row symbolic pass) on a sample of the batch and keeps the fastest per
-workload signature in a JSON cache.  Every candidate computes the same result
-(thresholds only decide which kernel handles a row); the tuner measures, it
-never changes the arithmetic."""
+"""Autotuner for batched products: searches launch parameters -- bin
+thresholds, which rows take the medium (256-thread) long-row workgroups, the
+shape and count of the symbolic long-row workgroups, the long-row LDS
+accumulator -- on a sample of the batch and keeps the fastest per workload
+signature in a JSON cache.  Every setting computes the same result
+(thresholds and shapes only decide which kernel and workgroup handle a row);
+the tuner measures, it never changes the arithmetic.
+
+The search is a coordinate descent over SPACE: starting from the library's
+defaults, each dimension in turn is set to each of its values with the
+others held at the best found so far, and the fastest is kept; passes repeat
+until one changes nothing (or `max_passes`).  Settings already timed are not
+timed again."""
 from __future__ import annotations
 
 import json
@@ -14,18 +21,16 @@ import torch
 
 from . import Batch
 
-# Candidate option sets (reap_options_t fields).  The first is the library's
-# default configuration.
-CANDIDATES = (
-    {},
-    {"wave_max_products": 512},
-    {"wave_max_products": -1},
-    {"wave_small_values": 64},
-    {"wave_hash_products": -1},
-    {"group_lds_span": 65536},
-    {"long_workgroups_per_cu": 1},
-    {"long_workgroups_per_cu": 4},
-    {"wave_max_products": -1, "long_workgroups_per_cu": 4},
+# Search space: one reap_options_t field per dimension and the values it may
+# take; the first value of each is the library default (0).
+SPACE = (
+    ("wave_max_products", (0, 512, -1)),      # wavefront rows: up to 1024 products, 512, or none
+    ("wave_small_values", (0, 64)),           # compact wavefront rows: up to 128 entries of C, or 64
+    ("wave_hash_products", (0, -1)),          # wavefront hash rows: up to 256 products, or none
+    ("mid_values", (0, 1024, -1)),            # medium long-row workgroups: rows up to 2048 entries, 1024, none
+    ("long_sym_narrow", (0, -1)),             # symbolic long-row workgroups: 256 threads when possible, or 512
+    ("long_workgroups_per_cu", (0, 1, 4)),    # symbolic long-row workgroups per CU: 2 (x2 narrow), 1, 4
+    ("group_lds_values", (0, 4096)),          # large long-row LDS accumulator: 8192 slots, or 4096
 )
 
 
@@ -37,7 +42,8 @@ def default_cache_path() -> str:
 def _load(path):
     try:
         with open(path) as f:
-            return json.load(f)
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
     except (OSError, ValueError):
         return {}
 
@@ -83,25 +89,58 @@ def lookup(signature: str, cache_path: str | None = None):
     return None
 
 
-def tune(As, Bs, dtype, signature: str, cache_path: str | None = None, reps: int = 2,
-         candidates=CANDIDATES, force: bool = False) -> dict:
+def _options(point) -> dict:
+    """reap_options_t fields of a point of the space (defaults left out)."""
+    return {k: v for k, v in point.items() if v != 0}
+
+
+def search(measure, space=SPACE, max_passes: int = 3):
+    """Coordinate descent over `space`; `measure(options)` returns seconds.
+    Returns (best options, best seconds, trials in the order timed)."""
+    point = {k: vals[0] for k, vals in space}
+    seen = {}
+    trials = []
+
+    def cost(pt):
+        key = tuple(sorted(_options(pt).items()))
+        if key not in seen:
+            s = float(measure(_options(pt)))
+            seen[key] = s
+            trials.append({"options": _options(pt), "seconds": s})
+        return seen[key]
+
+    best = cost(point)
+    for _ in range(max_passes):
+        changed = False
+        for name, vals in space:
+            for v in vals:
+                if v == point[name]:
+                    continue
+                cand = dict(point)
+                cand[name] = v
+                s = cost(cand)
+                if s < best:
+                    best, point, changed = s, cand, True
+        if not changed:
+            break
+    return _options(point), best, trials
+
+
+def tune(As, Bs, dtype, signature: str, cache_path: str | None = None, reps: int = 2, space=SPACE,
+         force: bool = False, max_passes: int = 3) -> dict:
     """Options for this workload: from a cache when `signature` is there
-    (unless `force`), else measured over `candidates` on (As, Bs) and written
-    to the user cache.  Returns {"options": ..., "seconds": ..., "trials": [...]}."""
+    (unless `force`), else searched over `space` on (As, Bs) and written to
+    the user cache.  Returns {"options": ..., "seconds": ..., "trials": [...]}."""
     path = cache_path or default_cache_path()
     if not force:
         entry = lookup(signature, path)
         if entry:
             return entry
-    cache = _load(path)
-    trials = []
-    for opts in candidates:
-        s = time_batch(As, Bs, dtype, opts, reps=reps)
-        trials.append({"options": dict(opts), "seconds": s})
-    best = min(trials, key=lambda t: t["seconds"])
-    entry = {"options": best["options"], "seconds": best["seconds"], "trials": trials,
+    opts, secs, trials = search(lambda o: time_batch(As, Bs, dtype, o, reps=reps), space, max_passes)
+    entry = {"options": opts, "seconds": secs, "trials": trials,
              "device": torch.cuda.get_device_name(0) if torch.cuda.is_available() else "",
-             "products": len(As)}
+             "products": len(As), "search": "coordinate descent over %d dimensions" % len(space)}
+    cache = _load(path)
     cache[signature] = entry
     _save(path, cache)
     return entry
