@@ -141,7 +141,9 @@ __device__ __forceinline__ long long block_excl_scan_i64(long long v, long long*
     if (lane == kWave - 1) s_red[w] = incl;
     __syncthreads();
     long long before = 0, all = 0;
-#pragma unroll
+    // partially unrolled: sixteen 64-bit partials loaded at once would take
+    // 32 registers at a point where the long-row kernels have none to spare
+#pragma unroll 4
     for (int x = 0; x < NT / kWave; ++x) {
         const long long t = s_red[x];
         before += (x < w) ? t : 0;
@@ -161,7 +163,9 @@ __device__ __forceinline__ long long block_excl_scan1_i64(long long v, long long
     if (lane == kWave - 1) buf[w] = incl;
     __syncthreads();
     long long before = 0, all = 0;
-#pragma unroll
+    // partially unrolled: sixteen 64-bit partials loaded at once would take
+    // 32 registers at a point where the long-row kernels have none to spare
+#pragma unroll 4
     for (int x = 0; x < NT / kWave; ++x) {
         const long long t = buf[x];
         before += (x < w) ? t : 0;

@@ -468,17 +468,17 @@ __global__ void __launch_bounds__(S::NT) k_long_num(NumArgs<T, IdxT, IdxC> p0,
         const int64_t cb = uniform((int64_t)p.c_rp[i]);
         const int64_t nc_row = uniform((int64_t)p.c_rp[i + 1]) - cb;
 
-        // a row of one block keeps its entry in registers and its full
-        // ranges published until a chunked accumulation replaces them
-        LongEnt en1{0, 0, 0.0};
+        // a row of one block keeps its full ranges published until a chunked
+        // accumulation replaces them (the entries are read again only then:
+        // holding them in registers through the row would spill)
         int64_t tot1 = 0;
         bool full1 = false;
-        if (nblk == 1) en1 = long_entry<NB, T, IdxT, true>(rs, nA, 0, p.a_col, p.a_val, p.b_rp);
         auto walk_all = [&](auto vals_tag, auto&& fn) {
             constexpr bool VL = decltype(vals_tag)::value;
             if (nblk == 1) {
                 if (!full1) {
-                    tot1 = flat_publish<NT, NB, true>(s_st, en1.b0, en1.len, en1.a, s_pub);
+                    const LongEnt en = long_entry<NB, T, IdxT, true>(rs, nA, 0, p.a_col, p.a_val, p.b_rp);
+                    tot1 = flat_publish<NT, NB, true>(s_st, en.b0, en.len, en.a, s_pub);
                     full1 = true;
                 }
                 flat_walk<VL ? kFlatU : kFlatUCols, NB, T, VL, true, false>(s_st, (int)nA, tot1, p.b_col, p.b_val, w,
@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(S::NT) k_long_num(NumArgs<T, IdxT, IdxC> p0,
                     s_bound[nch] = seg_hi;
                 }
                 {
-                    int r = rank0;
+                    int r = w0 < w1 ? (int)s_pfx[w0] : 0;   // this thread's first rank
                     for (int x = w0; x < w1; ++x) {
                         const int r0 = r;
                         const uint32_t bw = s_bits[x];
@@ -591,22 +591,34 @@ __global__ void __launch_bounds__(S::NT) k_long_num(NumArgs<T, IdxT, IdxC> p0,
                     const int r0 = c * V, rn = min(V, seg_nnz - r0);
                     auto add = [&](int col, double v) { atomicAdd(&s_vals[rank_of(col) - r0], v); };
                     for (int b = 0; b < nblk; ++b) {
-                        const LongEnt en = nblk == 1 ? en1 : long_entry<NB, T, IdxT, true>(rs, nA, b, p.a_col,
-                                                                                           p.a_val, p.b_rp);
-                        int64_t qlo = 0, qhi = 0;
+                        int64_t q = 0, len = 0;
+                        double a = 0.0;
                         if (pos_lds) {
+                            // from the stage this thread published for the previous
+                            // chunk (B entry b0 + its first position; the full
+                            // ranges, b0 itself, before the first chunk)
                             if ((int)threadIdx.x < ne1) {
-                                qlo = s_pos[c * ne1 + threadIdx.x];
-                                qhi = s_pos[(c + 1) * ne1 + threadIdx.x];
+                                const int x = threadIdx.x;
+                                const int32_t plo = s_pos[c * ne1 + x], phi = s_pos[(c + 1) * ne1 + x];
+                                const int32_t prev = c == 0 ? 0 : s_pos[(c - 1) * ne1 + x];
+                                q = s_st.qs[x] - prev + plo;
+                                len = phi - plo;
+                                a = s_st.a[x];
                             }
                         } else {
+                            const LongEnt en = long_entry<NB, T, IdxT, true>(rs, nA, b, p.a_col, p.a_val, p.b_rp);
                             const int32_t* brow = p.b_col + en.b0;
-                            qlo = lower_col(brow, 0, en.len, s_bound[c]);
-                            qhi = lower_col(brow, qlo, en.len, s_bound[c + 1]);
+                            const int64_t qlo = lower_col(brow, 0, en.len, s_bound[c]);
+                            const int64_t qhi = lower_col(brow, qlo, en.len, s_bound[c + 1]);
+                            q = en.b0 + qlo;
+                            len = qhi - qlo;
+                            a = en.a;
                         }
                         // the publication's barriers also order the previous chunk's
-                        // copy-out (and clearing) before this chunk's adds
-                        const int64_t tot = flat_publish<NT, NB, true>(s_st, en.b0 + qlo, qhi - qlo, en.a, s_pub);
+                        // copy-out (and clearing) before this chunk's adds; each
+                        // thread reads only its own stage slot above, before it
+                        // rewrites that slot here
+                        const int64_t tot = flat_publish<NT, NB, true>(s_st, q, len, a, s_pub);
                         const int ne = (int)min((int64_t)NB, nA - (int64_t)b * NB);
                         flat_walk<kFlatU, NB, T, true, true, false>(s_st, ne, tot, p.b_col, p.b_val, w, NW, add);
                     }
@@ -642,10 +654,14 @@ __global__ void __launch_bounds__(S::NT) k_long_num(NumArgs<T, IdxT, IdxC> p0,
                 if constexpr (sizeof(T) != sizeof(double))
                     for (int x = threadIdx.x; x < seg_nnz; x += NT) p.c_val[cb + off + x] = (T)acc[x];
             }
-            // columns in ascending order, thread t taking words t, t + NT, ...
-            // (neighbouring threads write neighbouring entries); the words are
-            // cleared for the next segment or row
-            for (int x = threadIdx.x; x < seg_w; x += NT) {
+            // columns in ascending order: wavefront w takes a contiguous block of
+            // words, its lanes words 64 apart inside it, so that a store
+            // instruction writes neighbouring entries and each stretch of C is
+            // written by one wavefront (no line is left half-written by
+            // several); the words are cleared for the next segment or row
+            const int wper = (seg_w + NW - 1) / NW;
+            const int wx1 = min(seg_w, (w + 1) * wper);
+            for (int x = w * wper + lane_id(); x < wx1; x += kWave) {
                 uint32_t bw = s_bits[x];
                 int64_t o = cb + off + s_pfx[x];
                 s_bits[x] = 0u;
