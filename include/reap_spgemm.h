@@ -208,8 +208,8 @@ reap_status_t reap_spgemm_symbolic(reap_spgemm_t plan, const reap_csr_t* A, cons
  * long-row list, scan partials, and for FP32 products the long-row FP64
  * accumulators when a long row reads a B row out of column order) is placed
  * in a static device array of REAP_NOALLOC_SCRATCH_BYTES (64 MiB) instead of
- * the plan's own allocation: about 22 bytes per row of A, so products up to
- * roughly 2.9 million rows.  Larger products return REAP_ERR_TOO_LARGE
+ * the plan's own allocation: about 29 bytes per row of A, so products up to
+ * roughly 2.3 million rows.  Larger products return REAP_ERR_TOO_LARGE
  * before any device work.  The call and the numeric call after it launch
  * their kernels directly (not through captured graphs, whatever the plan's
  * `graph` option) and call no hipMalloc, hipFree or other allocating
