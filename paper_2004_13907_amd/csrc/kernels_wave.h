@@ -19,10 +19,12 @@
 // Column sets live in a circular LDS bitmap of kWaveBitsWords 32-bit words
 // indexed by the absolute column (word (col >> 5) mod kWaveBitsWords), which
 // holds any row whose columns span fewer than kBmpMaxWords words: no window
-// offset is subtracted per product.  Word w is stored at position
-// w ^ (((w >> 7) & 3) << 2): the 4-word quads inside each 16-word block are
-// permuted by bits 7-8 of the word, so that words 128 apart (columns 4096
-// apart, the plane stride of a 64^3 stencil) fall in different LDS banks.
+// offset is subtracted per product.  In the numeric kernels word w is stored
+// at position w ^ (((w >> 7) & 3) << 2): the 4-word quads inside each 16-word
+// block are permuted by bits 7-8 of the word, so that words 128 apart
+// (columns 4096 apart, the plane stride of a 64^3 stencil) fall in different
+// LDS banks.  The symbolic kernel, whose time is its vector instructions,
+// stores word w at position w and keeps its bitmap zero between rows.
 // The numeric pass ranks each column by a prefix count per word taken in
 // window order from the row's first word, so the rank of a column is its
 // position in the sorted row (no sort).  Slots without a product aim at a
@@ -237,8 +239,9 @@ __device__ __forceinline__ void row_loads(const StEnt<IdxT, VALS>* ent, int nA, 
 }
 
 // Circular-bitmap position of slot (t, u): the word of its column (see the
-// file comment), or this lane's dummy word when the slot holds no product.
-template <int S>
+// file comment; SWZ: the numeric kernels' quad permutation), or this lane's
+// dummy word when the slot holds no product.
+template <int S, bool SWZ>
 __device__ __forceinline__ void slot_positions(const int32_t (&c)[S][kLaneEntries], const int (&rem)[S],
                                                int (&pos)[S][kLaneEntries]) {
     const int dummy = kWaveBitsWords + lane_id();
@@ -247,7 +250,7 @@ __device__ __forceinline__ void slot_positions(const int32_t (&c)[S][kLaneEntrie
 #pragma unroll
         for (int u = 0; u < kLaneEntries; ++u) {
             const uint32_t cc = (uint32_t)c[t][u];
-            const int ps = (int)(((cc >> 5) & kBmpMask) ^ ((cc >> 10) & 12u));
+            const int ps = SWZ ? (int)(((cc >> 5) & kBmpMask) ^ ((cc >> 10) & 12u)) : (int)((cc >> 5) & kBmpMask);
             pos[t][u] = u < rem[t] ? ps : dummy;
         }
     }
@@ -255,48 +258,66 @@ __device__ __forceinline__ void slot_positions(const int32_t (&c)[S][kLaneEntrie
 
 // Position of quad qd (words 4qd .. 4qd+3 of the circular order) in LDS: the
 // word swizzle moves whole quads (it flips word bits 2-3, i.e. quad bits 0-1).
+template <bool SWZ>
 __device__ __forceinline__ int bmp_quad_pos(int qd) {
     qd &= kBmpMask >> 2;
-    return qd ^ ((qd >> 5) & 3);
+    return SWZ ? qd ^ ((qd >> 5) & 3) : qd;
 }
 
 // Clears the quads holding window words [w0, w0 + nw) (nw <= kBmpMaxWords):
 // one 16-byte store per quad, consecutive quads on consecutive lanes.
+template <bool SWZ>
 __device__ __forceinline__ void bmp_clear(uint32_t* bits, int w0, int nw) {
     const int qa = w0 >> 2, nq = ((w0 + nw - 1) >> 2) - qa + 1;
     for (int x = lane_id(); x < nq; x += kWave)
-        *reinterpret_cast<uint4*>(bits + 4 * bmp_quad_pos(qa + x)) = make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4*>(bits + 4 * bmp_quad_pos<SWZ>(qa + x)) = make_uint4(0u, 0u, 0u, 0u);
 }
+
 
 // Sets the bit of every slot's column.  A lane's entries of one step are
 // consecutive entries of one B row, so neighbouring ones often share a word:
-// their bits are merged in registers and the word is updated once.
-template <int S>
+// their bits are merged in registers and the word is updated once.  With
+// UNCOND every slot still issues its OR, the merged ones into this lane's
+// dummy word (fewer vector instructions: the symbolic kernel); without, a
+// merged slot's lane sits out (fewer LDS accesses: the numeric kernels).
+template <int S, bool UNCOND>
 __device__ __forceinline__ void bmp_or(uint32_t* bits, const int32_t (&c)[S][kLaneEntries],
                                        const int (&pos)[S][kLaneEntries]) {
+    const int dummy = kWaveBitsWords + lane_id();
 #pragma unroll
     for (int t = 0; t < S; ++t) {
         uint32_t m[kLaneEntries];
+        int at[kLaneEntries];
 #pragma unroll
-        for (int u = 0; u < kLaneEntries; ++u) m[u] = 1u << (c[t][u] & 31);
+        for (int u = 0; u < kLaneEntries; ++u) {
+            m[u] = 1u << (c[t][u] & 31);
+            at[u] = pos[t][u];
+        }
 #pragma unroll
         for (int u = kLaneEntries - 1; u > 0; --u)
             if (pos[t][u] == pos[t][u - 1]) {
                 m[u - 1] |= m[u];
-                m[u] = 0u;
+                if (UNCOND)
+                    at[u] = dummy;
+                else
+                    m[u] = 0u;
             }
 #pragma unroll
         for (int u = 0; u < kLaneEntries; ++u)
-            if (m[u]) atomicOr(&bits[pos[t][u]], m[u]);
+            if (UNCOND || m[u]) atomicOr(&bits[at[u]], m[u]);
     }
 }
 
-// Set bits of the window's quads, summed over the wavefront.
-__device__ __forceinline__ int bmp_count(const uint32_t* bits, int w0, int nw) {
+// Set bits of the window's quads (unswizzled layout), summed over the
+// wavefront; each quad is cleared once read, so the bitmap is zero again for
+// the next row.
+__device__ __forceinline__ int bmp_count_clear(uint32_t* bits, int w0, int nw) {
     const int qa = w0 >> 2, nq = ((w0 + nw - 1) >> 2) - qa + 1;
     int pc = 0;
     for (int x = lane_id(); x < nq; x += kWave) {
-        const uint4 q = *reinterpret_cast<const uint4*>(bits + 4 * bmp_quad_pos(qa + x));
+        uint4* qp = reinterpret_cast<uint4*>(bits + 4 * bmp_quad_pos<false>(qa + x));
+        const uint4 q = *qp;
+        *qp = make_uint4(0u, 0u, 0u, 0u);
         pc += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
     }
     return dpp_reduce_sum(pc);
@@ -330,12 +351,10 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
     const int nw = (cmax >> 5) - (int)(cmin >> 5) + 1;
     if (nw <= kBmpMaxWords && (int64_t)cmax - (int64_t)cmin + 1 <= (int64_t)th.wave_max_span) {
         int pos[S][kLaneEntries];
-        slot_positions<S>(c, rem, pos);
-        bmp_clear(bits, (int)(cmin >> 5), nw);
+        slot_positions<S, false>(c, rem, pos);
+        bmp_or<S, true>(bits, c, pos);
         wave_sync();
-        bmp_or<S>(bits, c, pos);
-        wave_sync();
-        nnz = bmp_count(bits, (int)(cmin >> 5), nw);
+        nnz = bmp_count_clear(bits, (int)(cmin >> 5), nw);
         win = make_int2((int)cmin, nw);
         cls = nnz <= th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
     } else if (P <= th.wave_hash_products) {
@@ -367,6 +386,10 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
         }
         nnz = dpp_reduce_sum(mine);
         cls = kClsWaveHash;
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)   // the bitmap is zero between rows
+            *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) = make_uint4(0u, 0u, 0u, 0u);
     }
     wave_sync();
 }
@@ -391,7 +414,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     __shared__ int s_nnz[W];
     static_assert(W == 4, "tile sum adds four wavefronts");
 
-    const int w = threadIdx.x / kWave;
+    const int w = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
     const int gb = xcd_contiguous_block(blockIdx.x, gridDim.x);
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
@@ -400,6 +423,10 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     const int64_t row0 = ((int64_t)blk * W + w) * kRowsPerWave;
     uint32_t* bits = s_bits[w];
     auto& st = s_stage[w];
+    // the bitmap starts zero and every row leaves it zero (its count clears
+    // the window; the hash set clears its slots)
+    for (int x = lane; x < kBmpAlloc / 4; x += kWave)
+        *reinterpret_cast<uint4*>(bits + 4 * x) = make_uint4(0u, 0u, 0u, 0u);
 
     unsigned long long prod_acc = 0;
     unsigned int cnt[kNumClasses] = {0, 0, 0, 0, 0};
@@ -507,6 +534,13 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
     }
 }
 
+// The four 8-bit prefix counts of a word quad: r, r + s1, r + s2, r + s3
+// (s_k the set bits of the quad's first k words).
+__device__ __forceinline__ uint32_t pack_prefix4(int r, int s1, int s2, int s3) {
+    return (uint32_t)(r & 0xFF) | ((uint32_t)((r + s1) & 0xFF) << 8) | ((uint32_t)((r + s2) & 0xFF) << 16) |
+           ((uint32_t)((r + s3) & 0xFF) << 24);
+}
+
 // LDS of one wavefront of the compact bitmap numeric kernel.
 template <typename IdxT, int NCMAX>
 struct alignas(16) NumBmpLds {
@@ -534,34 +568,39 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
     const int64_t cb = uniform((int64_t)p.c_rp[i]);
     const int nc = (int)(uniform((int64_t)p.c_rp[i + 1]) - cb);
     // from the 16-aligned word where the prefix scan below starts
-    bmp_clear(sh.bits, lo_w & ~15, nw + (lo_w & 15));
+    bmp_clear<true>(sh.bits, lo_w & ~15, nw + (lo_w & 15));
     for (int x = lane; x < nc; x += kWave) sh.vals[x] = 0.0;
     int pos[S][kLaneEntries];
-    slot_positions<S>(c, rem, pos);
+    slot_positions<S, true>(c, rem, pos);
     wave_sync();
-    bmp_or<S>(sh.bits, c, pos);
+    bmp_or<S, false>(sh.bits, c, pos);
     wave_sync();
-    // prefix counts in window order, in rounds of 256 words over the window:
-    // in round j lane l takes word quad s0/4 + 64 j + l (s0 the row's first
-    // word rounded down to 16), so that the lanes' 16-byte reads and 4-byte
-    // writes are side by side in LDS; a wavefront scan gives each quad its
-    // prefix.
+    // prefix counts in window order, in rounds of 512 words over the window:
+    // in round j lane l takes the word quads s0/4 + 128 j + l and
+    // s0/4 + 128 j + 64 + l (s0 the row's first word rounded down to 16), so
+    // that the lanes' 16-byte reads and 4-byte writes are side by side in LDS;
+    // one wavefront scan of both quads' counts, packed as two 16-bit halves
+    // (a round holds at most 16384 bits), gives each quad its prefix.  Words
+    // past the window get prefixes too; no rank reads them.
     {
         const int q0 = ((lo_w & kBmpMask) & ~15) >> 2;   // first quad of the window
-        const int rounds = ((lo_w & 15) + nw + 4 * kWave - 1) / (4 * kWave);
+        const int rounds = ((lo_w & 15) + nw + 8 * kWave - 1) / (8 * kWave);
         int carry = 0;
         for (int j = 0; j < rounds; ++j) {
-            const int qp = bmp_quad_pos(q0 + j * kWave + lane);
-            const uint4 qv = *reinterpret_cast<const uint4*>(sh.bits + 4 * qp);
-            const int c0 = __popc(qv.x), c1 = __popc(qv.y), c2 = __popc(qv.z), c3 = __popc(qv.w);
-            const int tot = c0 + c1 + c2 + c3;
-            const int incl = dpp_incl_scan(tot);
-            const int r0 = carry + incl - tot;
-            carry += __builtin_amdgcn_readlane(incl, kWave - 1);
-            const uint32_t pk = (uint32_t)(r0 & 0xFF) | ((uint32_t)((r0 + c0) & 0xFF) << 8) |
-                                ((uint32_t)((r0 + c0 + c1) & 0xFF) << 16) |
-                                ((uint32_t)((r0 + c0 + c1 + c2) & 0xFF) << 24);
-            *reinterpret_cast<uint32_t*>(sh.pfx + 4 * qp) = pk;
+            const int qa = bmp_quad_pos<true>(q0 + j * 2 * kWave + lane);
+            const int qb = bmp_quad_pos<true>(q0 + j * 2 * kWave + kWave + lane);
+            const uint4 va = *reinterpret_cast<const uint4*>(sh.bits + 4 * qa);
+            const uint4 vb = *reinterpret_cast<const uint4*>(sh.bits + 4 * qb);
+            // running bit counts over each quad's words
+            const int a1 = __popc(va.x), a2 = a1 + __popc(va.y), a3 = a2 + __popc(va.z), ta = a3 + __popc(va.w);
+            const int b1 = __popc(vb.x), b2 = b1 + __popc(vb.y), b3 = b2 + __popc(vb.z), tb = b3 + __popc(vb.w);
+            const int incl = dpp_incl_scan(ta | (tb << 16));
+            const int all = __builtin_amdgcn_readlane(incl, kWave - 1);
+            const int ra = carry + (incl & 0xFFFF) - ta;
+            const int rb = carry + (all & 0xFFFF) + (incl >> 16) - tb;
+            carry += (all & 0xFFFF) + (all >> 16);
+            *reinterpret_cast<uint32_t*>(sh.pfx + 4 * qa) = pack_prefix4(ra, a1, a2, a3);
+            *reinterpret_cast<uint32_t*>(sh.pfx + 4 * qb) = pack_prefix4(rb, b1, b2, b3);
         }
     }
     wave_sync();
@@ -590,8 +629,10 @@ __device__ __forceinline__ void num_row_bmp(const NumArgs<T, IdxT, IdxC>& p, int
                     // bits of the word below the column (width taken mod 32 by the instruction)
                     const uint32_t below = __builtin_amdgcn_ubfe(rword[dt][u], 0u, (uint32_t)c[t][u]);
                     const int rk0 = (int)(rpfx[dt][u] & 0xFFu) + __popc(below);
-                    // rk0 < nc for every product whenever the pattern matches the symbolic pass
-                    const int rk = rk0 < nc ? rk0 : NCMAX + lane;
+                    // rk0 < nc for every product whenever the pattern matches the symbolic
+                    // pass; a larger rank lands in a slot that is never copied out (ranks
+                    // nc .. NCMAX - 1, or this lane's dummy)
+                    const int rk = min(rk0, NCMAX + lane);
                     atomicAdd(&sh.vals[rk], a[t] * (double)v[t][u]);
                     sh.cols[rk] = c[t][u];
                 }
@@ -619,7 +660,7 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
     static_assert(NCMAX < 255, "prefix counts are stored in 8 bits, 255 marks a dummy word");
     __shared__ __align__(16) NumBmpLds<IdxT, NCMAX> s_lds[W];
 
-    const int w = threadIdx.x / kWave;
+    const int w = uniform_i32(threadIdx.x / kWave);
     const int lane = lane_id();
     NumBmpLds<IdxT, NCMAX>& sh = s_lds[w];
     auto& st = sh.st;
