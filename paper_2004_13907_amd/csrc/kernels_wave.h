@@ -153,11 +153,24 @@ struct RowGeo {
     int q0;   // this lane's first offset inside its entry's B row
 };
 
+// kWave / G for G = g0 .. g0 + 7, one byte each (no division in the row setup).
+constexpr uint64_t pack_entries_per_step(int g0) {
+    uint64_t v = 0;
+    for (int x = 0; x < 8; ++x) v |= (uint64_t)(kWave / (g0 + x)) << (8 * x);
+    return v;
+}
+
+// L: the row's longest B row (at most kLaneEntries * 16 for the rows that
+// take this mapping); nA: its A entries (at most 64).  S is ceil(nA / E), or
+// kRowSteps + 1 for a row of more steps than a wavefront row takes.
 __device__ __forceinline__ RowGeo row_geo(int L, int nA) {
     RowGeo r;
-    const int G = max(1, (L + kLaneEntries - 1) / kLaneEntries);   // lanes per A entry, <= 16
-    r.E = kWave / G;
-    r.S = (nA + r.E - 1) / r.E;
+    const int G = min(max(1, (L + kLaneEntries - 1) / kLaneEntries), 16);   // lanes per A entry
+    const int gi = G - 1;
+    r.E = (int)(((gi < 8 ? pack_entries_per_step(1) : pack_entries_per_step(9)) >> (8 * (gi & 7))) & 0xFFu);
+    r.S = 1;
+#pragma unroll
+    for (int k = 1; k <= kRowSteps; ++k) r.S += nA > k * r.E ? 1 : 0;
     const int lane = lane_id();
     // lane / G exactly: (lane + 1/2) / G is at least 1/(2G) away from an integer
     r.g = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)G));
@@ -457,6 +470,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
         }
         uint8_t cls = kClsGroup;
         int nnz = 0;
+        int rowP = 0;   // the row's products, for the statistics of wavefront rows
         int2 win = make_int2(0, 0);
         if (nA == 0) {
             cls = kClsEmpty;
@@ -476,11 +490,7 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
                     case 3: sym_row<3, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
                     default: sym_row<4, IdxT, BUF>(ent, nA, P, rg, br, bits, p.th, cls, nnz, win); break;
                 }
-                if (cls != kClsGroup) {
-                    prod_acc += (unsigned long long)P;
-                    maxp = max(maxp, (unsigned)P);
-                    maxn = max(maxn, (unsigned)nnz);
-                }
+                rowP = P;
             }
         }
         if (lane == r) {
@@ -488,10 +498,19 @@ k_sym_wave(SymArgs<IdxT> p0, const SymArgs<IdxT>* __restrict__ P, BatchMap bm) {
             my_nnz = nnz;
             my_win = win;
         }
-        wave_nnz += cls == kClsGroup ? 0 : __builtin_amdgcn_readfirstlane(nnz);   // the wavefront's share of its scan tile's sum
+        // the statistics in scalar registers (the class, count and products are wavefront-uniform)
+        const int ucls = uniform_i32(cls), unnz = uniform_i32(nnz), uP = uniform_i32(rowP);
+        if (ucls != kClsGroup) {
+            wave_nnz += unnz;   // the wavefront's share of its scan tile's sum
+            if (ucls != kClsEmpty) {
+                prod_acc += (unsigned long long)uP;
+                maxp = max(maxp, (unsigned)uP);
+                maxn = max(maxn, (unsigned)unnz);
+            }
+        }
 #pragma unroll
-        for (int cl = 0; cl < kNumClasses; ++cl) cnt[cl] += (cls == cl) ? 1u : 0u;
-        if (cls == kClsGroup) group_flags |= 1u << r;
+        for (int cl = 0; cl < kNumClasses; ++cl) cnt[cl] += (ucls == cl) ? 1u : 0u;
+        if (ucls == kClsGroup) group_flags |= 1u << r;
     }
     if (lane < nrows) {
         p.cls[row0 + lane] = my_cls;
