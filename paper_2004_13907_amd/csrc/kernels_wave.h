@@ -118,6 +118,82 @@ __device__ __forceinline__ bool stage_chunk(ChunkStage<IdxT, VALS, ROWS, CAP>& s
     return true;
 }
 
+// Stages the rows row0 + r * stride (r < nrows <= ROWS) as stage_chunk stages
+// consecutive rows (entry offsets per row in rowoff).  Returns false (nothing
+// staged) when they have more than CAP entries.
+template <typename T, typename IdxT, bool VALS, int ROWS, int CAP>
+__device__ __forceinline__ bool stage_rows_strided(ChunkStage<IdxT, VALS, ROWS, CAP>& st, int64_t row0, int stride,
+                                                   int nrows, const IdxT* __restrict__ a_rp,
+                                                   const int32_t* __restrict__ a_col, const T* __restrict__ a_val,
+                                                   const IdxT* __restrict__ b_rp) {
+    const int lane = lane_id();
+    int64_t beg = 0, len = 0;
+    if (lane < nrows) {
+        const int64_t i = row0 + (int64_t)lane * stride;
+        beg = (int64_t)a_rp[i];
+        len = (int64_t)a_rp[i + 1] - beg;
+    }
+    // each row's first A entry and its offset in the stage (wavefront-uniform)
+    int64_t begs[ROWS];
+    int64_t offs[ROWS + 1];
+    offs[0] = 0;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        begs[r] = uniform_i64(shfl(beg, r));
+        offs[r + 1] = offs[r] + (r < nrows ? uniform_i64(shfl(len, r)) : (int64_t)0);
+    }
+    const int64_t E = offs[ROWS];
+    if (E > CAP) return false;
+    if (lane <= ROWS) {
+        int64_t o = offs[0];
+#pragma unroll
+        for (int r = 1; r <= ROWS; ++r) o = lane == r ? offs[r] : o;
+        st.rowoff[lane] = (int32_t)o;
+    }
+    constexpr int U = (CAP + kWave - 1) / kWave;
+    int k[U];
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int x = u * kWave + lane;
+        k[u] = 0;
+        a[u] = 0.0;
+        if (x < E) {
+            // the row of stage entry x and its place in A
+            int64_t src = begs[0] + x;
+#pragma unroll
+            for (int r = 1; r < ROWS; ++r)
+                if (x >= offs[r]) src = begs[r] + (x - offs[r]);
+            k[u] = a_col[src];
+            if (VALS) a[u] = (double)a_val[src];
+        }
+    }
+    IdxT x0[U], x1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int x = u * kWave + lane;
+        x0[u] = 0;
+        x1[u] = 0;
+        if (x < E) {
+            x0[u] = b_rp[k[u]];
+            x1[u] = b_rp[k[u] + 1];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int x = u * kWave + lane;
+        if (x < E) {
+            StEnt<IdxT, VALS> en;
+            en.b0 = x0[u];
+            en.len = (int32_t)min((int64_t)x1[u] - (int64_t)x0[u], (int64_t)(1 << 24));
+            if constexpr (VALS) en.a = a[u];
+            st.ent[x] = en;
+        }
+    }
+    wave_sync();
+    return true;
+}
+
 // Stages the entries of one row (at most 64) at the start of the stage.
 template <typename T, typename IdxT, bool VALS, int ROWS, int CAP>
 __device__ __forceinline__ void stage_row(ChunkStage<IdxT, VALS, ROWS, CAP>& st, IdxT rs, int nA,
@@ -689,22 +765,26 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
     const int q = TAB && bm.nprod > 1 ? find_product(bm.blk_start, bm.nprod, gb) : 0;
     const int blk = gb - (TAB && bm.nprod > 1 ? bm.blk_start[q] : 0);
     const NumArgs<T, IdxT, IdxC> p = TAB ? P[q] : p0;
-    const int64_t rowc = ((int64_t)blk * W + w) * kRowsPerWave;
-    const int nall = (int)max((int64_t)0, min((int64_t)kRowsPerWave, p.m - rowc));
-    const uint64_t todo_all = ballot(lane < nall && p.cls[rowc + lane] == want);
+    // the workgroup's rows rb .. rb + W * kRowsPerWave - 1, interleaved: row j
+    // of wavefront w is rb + w + W * j, so that the wavefronts of a workgroup
+    // work on neighbouring rows at the same time and share in L1 the B rows
+    // those read
+    const int64_t rb = (int64_t)blk * W * kRowsPerWave;
+    const int64_t my_row = rb + w + (int64_t)W * lane;
+    const uint64_t todo_all = ballot(lane < kRowsPerWave && my_row < p.m && p.cls[my_row] == want);
     if (!todo_all) return;
     const BReader<T, BUF> br(p.b_col, p.b_val, (int64_t)uniform(p.b_rp[p.k]));
 
     for (int h = 0; h < kRowsPerWave / kNumStageRows; ++h) {
-        const int64_t row0 = rowc + h * kNumStageRows;
+        const int64_t row0 = rb + w + (int64_t)W * (h * kNumStageRows);
         uint64_t todo = (todo_all >> (h * kNumStageRows)) & ((1ull << kNumStageRows) - 1);
         if (!todo) continue;
-        const int nrows = (int)max((int64_t)0, min((int64_t)kNumStageRows, p.m - row0));
-        const bool staged = stage_chunk<T, IdxT, true>(st, row0, nrows, p.a_rp, p.a_col, p.a_val, p.b_rp);
+        const int nrows = (int)max((int64_t)0, min((int64_t)kNumStageRows, (p.m - row0 + W - 1) / W));
+        const bool staged = stage_rows_strided<T, IdxT, true>(st, row0, W, nrows, p.a_rp, p.a_col, p.a_val, p.b_rp);
         while (todo) {
             const int r = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
-            const int64_t i = row0 + r;
+            const int64_t i = row0 + (int64_t)W * r;
             int nA, off;
             if (staged) {
                 off = uniform_i32(st.rowoff[r]);
