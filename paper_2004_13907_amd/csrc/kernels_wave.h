@@ -266,24 +266,53 @@ struct BReader;
 
 template <typename T>
 struct BReader<T, true> {
+    static_assert(kLaneEntries == 4, "a lane's entries are one 16-byte load per array");
     __amdgpu_buffer_rsrc_t col, val;
-    __device__ __forceinline__ BReader(const int32_t* c, const T* v, int64_t nnz) {
+    int64_t n;   // entries of B
+    __device__ __forceinline__ BReader(const int32_t* c, const T* v, int64_t nnz) : n(nnz) {
         col = __builtin_amdgcn_make_buffer_rsrc((void*)c, (short)0, (int)(nnz * 4), kBufferWord3);
         val = __builtin_amdgcn_make_buffer_rsrc((void*)v, (short)0, (int)(nnz * (int64_t)sizeof(T)), kBufferWord3);
     }
+    // With values, a lane's four entries are one 16-byte load of columns and
+    // one (FP32) or two (FP64) of values, written out: the vector memory unit's
+    // work goes by instructions, and the compiler does not merge the
+    // per-entry loads there by itself.  A lane whose four entries would pass
+    // B's last one reads them one by one (each read past the range returns 0).
+    // Columns alone are read entry by entry (merged by the compiler; the
+    // symbolic kernel, bound by its vector instructions, keeps no range test).
     template <bool VALS>
     __device__ __forceinline__ void load(int64_t base, int32_t (&c)[kLaneEntries], T (&v)[kLaneEntries]) const {
         const int oc = (int)base * 4;
+        const int ov = (int)base * (int)sizeof(T);
+        if (VALS && base + kLaneEntries <= n) {
+            const auto qc = __builtin_amdgcn_raw_buffer_load_b128(col, oc, 0, 0);
 #pragma unroll
-        for (int u = 0; u < kLaneEntries; ++u) c[u] = __builtin_amdgcn_raw_buffer_load_b32(col, oc + 4 * u, 0, 0);
-        if constexpr (VALS) {
-            const int ov = (int)base * (int)sizeof(T);
+            for (int u = 0; u < kLaneEntries; ++u) c[u] = (int32_t)qc[u];
+            if constexpr (VALS) {
+                if constexpr (sizeof(T) == 8) {
+                    const auto q0 = __builtin_amdgcn_raw_buffer_load_b128(val, ov, 0, 0);
+                    const auto q1 = __builtin_amdgcn_raw_buffer_load_b128(val, ov + 16, 0, 0);
+                    v[0] = __builtin_bit_cast(T, ((uint64_t)(uint32_t)q0[1] << 32) | (uint32_t)q0[0]);
+                    v[1] = __builtin_bit_cast(T, ((uint64_t)(uint32_t)q0[3] << 32) | (uint32_t)q0[2]);
+                    v[2] = __builtin_bit_cast(T, ((uint64_t)(uint32_t)q1[1] << 32) | (uint32_t)q1[0]);
+                    v[3] = __builtin_bit_cast(T, ((uint64_t)(uint32_t)q1[3] << 32) | (uint32_t)q1[2]);
+                } else {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b128(val, ov, 0, 0);
 #pragma unroll
-            for (int u = 0; u < kLaneEntries; ++u) {
-                if constexpr (sizeof(T) == 8)
-                    v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(val, ov + 8 * u, 0, 0));
-                else
-                    v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(val, ov + 4 * u, 0, 0));
+                    for (int u = 0; u < kLaneEntries; ++u) v[u] = __builtin_bit_cast(T, (uint32_t)q[u]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kLaneEntries; ++u) c[u] = __builtin_amdgcn_raw_buffer_load_b32(col, oc + 4 * u, 0, 0);
+            if constexpr (VALS) {
+#pragma unroll
+                for (int u = 0; u < kLaneEntries; ++u) {
+                    if constexpr (sizeof(T) == 8)
+                        v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(val, ov + 8 * u, 0, 0));
+                    else
+                        v[u] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(val, ov + 4 * u, 0, 0));
+                }
             }
         }
     }

@@ -74,6 +74,33 @@ def check_full(reap, A, B, dtype=torch.float64, label="", expect=None, **kw):
     return compare_full(ref, rp, col, val, npdt, label), ref
 
 
+def _tail_case(last_len: int, seed: int, dtype):
+    """B whose last row has ``last_len`` entries (so that a lane's four
+    consecutive B entries straddle the end of B in every way), and an A whose
+    rows read that last row alone, with the row before it, and with all rows."""
+    rng = np.random.default_rng(seed)
+    nb, n = 6, 40
+    lens = np.concatenate([rng.integers(3, 13, nb - 1), [last_len]]).astype(np.int64)
+    cols = np.concatenate([np.sort(rng.choice(n, int(k), replace=False)) for k in lens]).astype(np.int32)
+    B = synth.CSR(nb, n, np.concatenate([[0], np.cumsum(lens)]).astype(np.int32), cols,
+                  rng.uniform(-1, 1, int(lens.sum())).astype(dtype))
+    a_rows = [[nb - 1], [nb - 2, nb - 1], list(range(nb)), []]
+    a_rp = np.concatenate([[0], np.cumsum([len(r) for r in a_rows])]).astype(np.int32)
+    a_col = np.array([c for r in a_rows for c in r], dtype=np.int32)
+    A = synth.CSR(len(a_rows), nb, a_rp, a_col, rng.uniform(-1, 1, len(a_col)).astype(dtype))
+    return A, B
+
+
+@pytest.mark.parametrize("path", ["default", "hash"])
+def test_b_tail_entries(reap, path):
+    """Lanes whose four B entries pass the end of B read them one by one; the
+    entries inside B must still be read (every last-row length 1..9, FP64 and FP32)."""
+    for last_len in range(1, 10):
+        for dtype, tdt in ((np.float64, torch.float64), (np.float32, torch.float32)):
+            A, B = _tail_case(last_len, 900 + last_len, dtype)
+            check_full(reap, A, B, dtype=tdt, label="B tail %d %s %s" % (last_len, path, tdt), **PATHS[path])
+
+
 # --- workload configurations ------------------------------------------------
 
 def test_uniform_config(reap):
