@@ -84,7 +84,8 @@ typedef struct {
  *   wave_max_span     -- widest column window (max col - min col + 1) a
  *                        wavefront handles with a bitmap (<= 32768; 0 = default).
  *   wave_hash_products-- rows wider than that window but with at most this many
- *                        products use a wavefront hash table (<= 256; 0 = default).
+ *                        products use a wavefront hash table (<= half of
+ *                        wave_hash_slots; 0 = default, that half).
  *   group_lds_span    -- columns per segment of a long row's window: a long
  *                        row's LDS bitmap covers this many columns at a time
  *                        and wider windows are processed segment by segment
@@ -131,6 +132,10 @@ typedef struct {
  *                        workgroups with a 65536-column bitmap (twice as
  *                        many per CU) when every product of the call has at
  *                        most 65536 columns: 0 = yes (default), negative = no.
+ *   wave_hash_slots   -- LDS hash-table slots of the wavefront hash class:
+ *                        512 (default, any value other than 1024) or 1024;
+ *                        rows of at most half as many products qualify
+ *                        (wave_hash_products defaults to that half).
  * For every threshold, 0 selects the default and a negative value 0.
  */
 typedef struct {
@@ -148,7 +153,8 @@ typedef struct {
     int32_t scan_onepass_tiles;
     int32_t mid_values;
     int32_t long_sym_narrow;
-    int32_t reserved[2];
+    int32_t wave_hash_slots;
+    int32_t reserved[1];
 } reap_options_t;
 
 /*

@@ -70,7 +70,8 @@ class reap_options_t(ctypes.Structure):
         ("scan_onepass_tiles", ctypes.c_int32),
         ("mid_values", ctypes.c_int32),
         ("long_sym_narrow", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("wave_hash_slots", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 

@@ -26,7 +26,8 @@ from . import Batch
 SPACE = (
     ("wave_max_products", (0, 512, -1)),      # wavefront rows: up to 1024 products, 512, or none
     ("wave_small_values", (0, 64)),           # compact wavefront rows: up to 128 entries of C, or 64
-    ("wave_hash_products", (0, -1)),          # wavefront hash rows: up to 256 products, or none
+    ("wave_hash_products", (0, -1)),          # wavefront hash rows: up to half the table's slots, or none
+    ("wave_hash_slots", (0, 1024)),           # wavefront hash table: 512 slots, or 1024 (rows up to 512 products)
     ("mid_values", (0, 1024, -1)),            # medium long-row workgroups: rows up to 2048 entries, 1024, none
     ("long_sym_narrow", (0, -1)),             # symbolic long-row workgroups: 256 threads when possible, or 512
     ("long_workgroups_per_cu", (0, 1, 4)),    # symbolic long-row workgroups per CU: 2 (x2 narrow), 1, 4

@@ -476,9 +476,10 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
         win = make_int2((int)cmin, nw);
         cls = nnz <= th.wave_small_nnz ? kClsWaveBmpS : kClsGroup;
     } else if (P <= th.wave_hash_products) {
-        // an LDS hash set of the row's columns (the bitmap area, kWaveHashSlots keys)
-#pragma unroll
-        for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)
+        // an LDS hash set of the row's columns in the bitmap area (1 << th.wave_hash_log2
+        // keys, the numeric kernel's table size; at most twice the row's products)
+        const int hlog = th.wave_hash_log2, hslots = 1 << hlog;
+        for (int j = 0; j < hslots / (4 * kWave); ++j)
             *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) =
                 make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
         wave_sync();
@@ -489,7 +490,7 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
             for (int u = 0; u < kLaneEntries; ++u) {
                 const uint32_t key = (uint32_t)c[t][u];
                 if (u < rem[t]) {
-                    uint32_t h = hash_col((int)key) >> (32 - 9);
+                    uint32_t h = hash_col((int)key) >> (32 - hlog);
                     while (true) {
                         const uint32_t old = atomicCAS(&bits[h], 0xFFFFFFFFu, key);
                         if (old == 0xFFFFFFFFu) {
@@ -497,7 +498,7 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
                             break;
                         }
                         if (old == key) break;
-                        h = (h + 1) & (kWaveHashSlots - 1);
+                        h = (h + 1) & (hslots - 1);
                     }
                 }
             }
@@ -506,7 +507,7 @@ __device__ __forceinline__ void sym_row(const StEnt<IdxT, false>* ent, int nA, i
         cls = kClsWaveHash;
         wave_sync();
 #pragma unroll
-        for (int j = 0; j < kWaveHashSlots / (4 * kWave); ++j)   // the bitmap is zero between rows
+        for (int j = 0; j < hslots / (4 * kWave); ++j)   // the bitmap is zero between rows
             *reinterpret_cast<uint4*>(bits + 4 * (j * kWave + lane)) = make_uint4(0u, 0u, 0u, 0u);
     }
     wave_sync();
@@ -837,16 +838,18 @@ k_num_wave_bmp(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restri
     }
 }
 
-// Numeric work of one hash-class row of S steps: LDS hash table keyed by
-// column, then the occupied slots are compacted and each entry is placed by
-// counting the smaller columns.
-template <int S, typename T, typename IdxT, typename IdxC, bool BUF>
+// Numeric work of one hash-class row of S steps: an LDS hash table of HS
+// slots keyed by column (rows of at most HS / 2 products), then the occupied
+// slots are compacted to the front of the same table and each entry is
+// placed by counting the smaller columns.
+template <int S, int HS, typename T, typename IdxT, typename IdxC, bool BUF>
 __device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, int64_t i,
                                              const StEnt<IdxT, true>* ent, int nA, const RowGeo& rg,
-                                             const BReader<T, BUF>& br, uint32_t* keys, double* hv, int32_t* ck,
-                                             double* cv) {
-    constexpr int NC = kWaveHashProducts;
+                                             const BReader<T, BUF>& br, uint32_t* keys, double* hv) {
+    constexpr int NC = HS / 2;
     constexpr int NCU = NC / kWave;
+    constexpr int LOG = HS == 1024 ? 10 : 9;
+    static_assert(HS == (1 << LOG), "512 or 1024 slots");
     constexpr uint32_t kEmpty = 0xFFFFFFFFu;
     const int lane = lane_id();
     int32_t c[S][kLaneEntries];
@@ -855,7 +858,7 @@ __device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, in
     double a[S];
     row_loads<S, T, IdxT, true, BUF>(ent, nA, rg, br, c, v, rem, a);
     const int64_t cb = uniform((int64_t)p.c_rp[i]);
-    for (int x = lane; x < kWaveHashSlots; x += kWave) {
+    for (int x = lane; x < HS; x += kWave) {
         keys[x] = kEmpty;
         hv[x] = 0.0;
     }
@@ -866,41 +869,46 @@ __device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, in
         for (int u = 0; u < kLaneEntries; ++u) {
             if (u < rem[t]) {
                 const uint32_t key = (uint32_t)c[t][u];
-                uint32_t hs = hash_col((int)key) >> (32 - 9);
+                uint32_t hs = hash_col((int)key) >> (32 - LOG);
                 while (true) {
                     const uint32_t old = atomicCAS(&keys[hs], kEmpty, key);
                     if (old == kEmpty || old == key) break;
-                    hs = (hs + 1) & (kWaveHashSlots - 1);
+                    hs = (hs + 1) & (HS - 1);
                 }
                 atomicAdd(&hv[hs], a[t] * (double)v[t][u]);
             }
         }
     }
     wave_sync();
+    // compaction in place: an entry moves to a slot at or before its own, and
+    // every lane reads its slot before any lane writes
     int nc = 0;
-    for (int x0 = 0; x0 < kWaveHashSlots; x0 += kWave) {
+    for (int x0 = 0; x0 < HS; x0 += kWave) {
         const int x = x0 + lane;
-        const bool occ = keys[x] != kEmpty;
+        const uint32_t kx = keys[x];
+        const double vx = hv[x];
+        const bool occ = kx != kEmpty;
         const uint64_t om = ballot(occ);
+        wave_sync();
         if (occ && nc + mbcnt(om) < NC) {
             const int pos = nc + mbcnt(om);
-            ck[pos] = (int32_t)keys[x];
-            cv[pos] = hv[x];
+            keys[pos] = kx;
+            hv[pos] = vx;
         }
         nc += __popcll(om);
+        wave_sync();
     }
     nc = min(nc, NC);
-    wave_sync();
     int key[NCU];
     int rank[NCU];
 #pragma unroll
     for (int u = 0; u < NCU; ++u) {
         const int e = u * kWave + lane;
-        key[u] = (e < nc) ? ck[e] : INT32_MAX;
+        key[u] = (e < nc) ? (int)keys[e] : INT32_MAX;
         rank[u] = 0;
     }
     for (int j = 0; j < nc; ++j) {
-        const int kj = ck[j];
+        const int kj = (int)keys[j];
 #pragma unroll
         for (int u = 0; u < NCU; ++u) rank[u] += (kj < key[u]) ? 1 : 0;
     }
@@ -909,7 +917,7 @@ __device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, in
         const int e = u * kWave + lane;
         if (e < nc) {
             p.c_col[cb + rank[u]] = key[u];
-            p.c_val[cb + rank[u]] = (T)cv[e];
+            p.c_val[cb + rank[u]] = (T)hv[e];
         }
     }
     wave_sync();
@@ -917,15 +925,12 @@ __device__ __forceinline__ void num_row_hash(const NumArgs<T, IdxT, IdxC>& p, in
 
 // ---------------------------------------------------------------------------
 // Numeric, one wavefront per row whose columns span too wide a window for the
-// bitmap (at most kWaveHashProducts products).
-template <typename T, typename IdxT, typename IdxC, int W, bool TAB, bool BUF>
+// bitmap (at most HS / 2 products; HS = 512 or 1024 hash slots).
+template <typename T, typename IdxT, typename IdxC, int W, bool TAB, bool BUF, int HS>
 __global__ void __launch_bounds__(W * 64)
 k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restrict__ P, BatchMap bm, uint8_t want) {
-    constexpr int NC = kWaveHashProducts;
-    __shared__ __align__(16) uint32_t s_keys[W][kWaveHashSlots];
-    __shared__ double s_hv[W][kWaveHashSlots];
-    __shared__ int32_t s_ck[W][NC];
-    __shared__ double s_cv[W][NC];
+    __shared__ __align__(16) uint32_t s_keys[W][HS];
+    __shared__ double s_hv[W][HS];
     __shared__ __align__(16) ChunkStage<IdxT, true, kNumStageRows, kNumStageCap> s_stage[W];
 
     const int w = threadIdx.x / kWave;
@@ -968,10 +973,10 @@ k_num_wave_hash(NumArgs<T, IdxT, IdxC> p0, const NumArgs<T, IdxT, IdxC>* __restr
             uint32_t* keys = s_keys[w];
             double* hv = s_hv[w];
             switch (rg.S) {
-                case 1: num_row_hash<1, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
-                case 2: num_row_hash<2, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
-                case 3: num_row_hash<3, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
-                default: num_row_hash<4, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv, s_ck[w], s_cv[w]); break;
+                case 1: num_row_hash<1, HS, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv); break;
+                case 2: num_row_hash<2, HS, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv); break;
+                case 3: num_row_hash<3, HS, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv); break;
+                default: num_row_hash<4, HS, T, IdxT, IdxC, BUF>(p, i, ent, nA, rg, br, keys, hv); break;
             }
         }
     }

@@ -846,6 +846,24 @@ reap_status_t symbolic_batch(reap_spgemm_s* p, int64_t count, const reap_csr_t* 
 // ---------------------------------------------------------------------------
 // Numeric pass.
 
+// The hash-class numeric kernel with an HS-slot table.
+template <typename T, typename IdxT, typename IdxC, int HS>
+void launch_num_hash(reap_spgemm_s* p, bool tab, dim3 grid, dim3 block, const NumArgs<T, IdxT, IdxC>& a0,
+                     const NumArgs<T, IdxT, IdxC>* P, const BatchMap& bm, uint8_t want) {
+    if (tab && p->buf_b)
+        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, true, HS>), grid, block, 0, p->stream, a0,
+                           P, bm, want);
+    else if (tab)
+        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, false, HS>), grid, block, 0, p->stream,
+                           a0, P, bm, want);
+    else if (p->buf_b)
+        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, true, HS>), grid, block, 0, p->stream,
+                           a0, P, bm, want);
+    else
+        hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, false, HS>), grid, block, 0, p->stream,
+                           a0, P, bm, want);
+}
+
 template <typename T, typename IdxT, typename IdxC>
 reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0) {
     const bool tab = use_tables(p);
@@ -884,18 +902,10 @@ reap_status_t launch_numeric(reap_spgemm_s* p, const NumArgs<T, IdxT, IdxC>& a0)
     if (p->agg.cls[kClsWaveHash] > 0) {
         const dim3 grid(p->total_blocks), block(kNumWavesH * kWave);
         const uint8_t want = kClsWaveHash;
-        if (tab && p->buf_b)
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, true>), grid, block, 0, p->stream,
-                               a0, P, bm, want);
-        else if (tab)
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, true, false>), grid, block, 0, p->stream,
-                               a0, P, bm, want);
-        else if (p->buf_b)
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, true>), grid, block, 0, p->stream,
-                               a0, P, bm, want);
+        if (p->th.wave_hash_log2 == 10)
+            launch_num_hash<T, IdxT, IdxC, kWaveHashSlotsMax>(p, tab, grid, block, a0, P, bm, want);
         else
-            hipLaunchKernelGGL((k_num_wave_hash<T, IdxT, IdxC, kNumWavesH, false, false>), grid, block, 0, p->stream,
-                               a0, P, bm, want);
+            launch_num_hash<T, IdxT, IdxC, kWaveHashSlots>(p, tab, grid, block, a0, P, bm, want);
         REAP_LAUNCH_CHECK();
         debug_step(p, "k_num_wave_hash");
     }
@@ -1163,7 +1173,9 @@ reap_status_t reap_spgemm_create(reap_spgemm_t* plan, reap_dtype_t dtype, reap_i
     if (p->debug_sync) p->use_graph = false;
     p->th.wave_max_products = clampi(o.wave_max_products, 0, kWaveMaxProducts, kWaveMaxProducts);
     p->th.wave_max_span = clampi(o.wave_max_span, 0, 32 * kWaveBitsWords, 32 * kWaveBitsWords);
-    p->th.wave_hash_products = clampi(o.wave_hash_products, 0, kWaveHashProducts, kWaveHashProducts);
+    p->th.wave_hash_log2 = o.wave_hash_slots == kWaveHashSlotsMax ? 10 : 9;
+    p->th.wave_hash_products = clampi(o.wave_hash_products, 0, (1 << p->th.wave_hash_log2) / 2,
+                                      (1 << p->th.wave_hash_log2) / 2);
     p->th.wave_small_nnz = clampi(o.wave_small_values, 0, kWaveSmallNnz, kWaveSmallNnz);
     p->th.group_lds_span = clampi(o.group_lds_span, 32, 32 * kGroupBitsWords, 32 * kGroupBitsWords) / 32 * 32;
     p->th.group_lds_values = clampi(o.group_lds_values, kLongMinVals, kLongVals, kLongVals);

@@ -37,8 +37,9 @@ enum RowClass : uint8_t {
 constexpr int kWaveMaxProducts = 1024;   // product slots of a wavefront row (16 per lane)
 constexpr int kWaveBitsWords = 1024;     // circular bitmap of the wavefront kernels: 32768 columns
 constexpr int kWaveSmallNnz = 128;       // entries of C a wavefront numeric row holds
-constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products
-constexpr int kWaveHashSlots = 512;      // load factor <= 1/2
+constexpr int kWaveHashProducts = 256;   // hash rows: at most 256 products (the default table)
+constexpr int kWaveHashSlots = 512;      // default hash table: load factor <= 1/2
+constexpr int kWaveHashSlotsMax = 1024;  // the larger table (rows of at most 512 products)
 constexpr int kGroupBitsWords = 8192;    // 262144-column LDS bitmap segment of a long row
 constexpr int kRowsPerWave = 8;          // consecutive rows a wavefront walks through
 constexpr int kStageCap = 256;           // A entries of one chunk of rows staged in LDS (symbolic)
@@ -121,7 +122,8 @@ constexpr int kLongCtrWords = 8;
 struct Thresholds {
     int wave_max_products;   // <= kWaveMaxProducts
     int wave_max_span;       // <= 32 * kWaveBitsWords
-    int wave_hash_products;  // <= kWaveHashProducts
+    int wave_hash_products;  // <= (1 << wave_hash_log2) / 2
+    int wave_hash_log2;      // hash-class table: 9 (512 slots) or 10 (1024 slots)
     int wave_small_nnz;      // <= kWaveSmallNnz
     int group_lds_span;      // <= 32 * kGroupBitsWords, multiple of 32
     int group_lds_values;    // FP64 LDS slots per rank chunk of a long row, kLongMinVals..kLongVals

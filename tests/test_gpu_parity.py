@@ -101,6 +101,17 @@ def test_b_tail_entries(reap, path):
             check_full(reap, A, B, dtype=tdt, label="B tail %d %s %s" % (last_len, path, tdt), **PATHS[path])
 
 
+def test_hash_table_sizes(reap):
+    """Rows of 400 products over a window too wide for the bitmap: long rows
+    with the 512-slot hash table (rows of at most 256 products), wavefront hash
+    rows with the 1024-slot one; both against the oracle."""
+    A = synth.uniform_rows(300, 20000, 20, seed=11)
+    B = synth.uniform_rows(20000, 40000, 20, seed=12)
+    check_full(reap, A, B, label="hash 512", expect=lambda st: st["wave_hash"] == 0 and st["group"] == A.rows)
+    check_full(reap, A, B, label="hash 1024", wave_hash_slots=1024,
+               expect=lambda st: st["wave_hash"] == A.rows and st["group"] == 0)
+
+
 # --- workload configurations ------------------------------------------------
 
 def test_uniform_config(reap):
@@ -166,6 +177,7 @@ PATHS = {
     "default": {},
     "all_group": {"wave_max_products": -1},
     "hash": {"wave_max_span": -1},
+    "hash_1024": {"wave_max_span": -1, "wave_hash_slots": 1024},
     "small_cap": {"wave_small_values": -1},
     "group_segments": {"wave_max_products": -1, "group_lds_span": 64},
     "group_segments_mixed": {"wave_max_products": 8, "group_lds_span": 96},
@@ -185,6 +197,7 @@ PATH_EXPECT = {
     # entries: the long rows are medium rows
     "all_group": lambda st: _all_long(st) and st["group_medium"] == st["group"],
     "hash": lambda st: st["wave_bitmap"] == 0,
+    "hash_1024": lambda st: st["wave_bitmap"] == 0,
     "small_cap": lambda st: st["wave_bitmap"] == 0 and st["group"] > 0,
     "group_segments": lambda st: _all_long(st) and st["long_segments_lds"] + st["long_segments_chunked"]
     + st["long_segments_device"] > st["group"],
