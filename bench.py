@@ -214,7 +214,7 @@ def run_batched(args):
     tune_path = os.path.join(ROOT, "gpurun_out", "autotune.json") if os.path.isdir(
         os.path.join(ROOT, "gpurun_out")) else None
     tuned = autotune.tune([As[q] for q in sample], [Bs[q] for q in sample], torch.float64, sig,
-                          cache_path=tune_path)
+                          cache_path=tune_path, force=args.retune)
     opts = dict(tuned["options"])
     log("autotuned options", opts, "(%.3f s on the sample)" % tuned["seconds"])
 
@@ -454,6 +454,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0,
                     help="batched: device bytes of C (plus workspace) admitted per wave")
     ap.add_argument("--no-plain", action="store_true", help="batched: skip the one-product-at-a-time comparison")
+    ap.add_argument("--retune", action="store_true",
+                    help="batched: search the options again instead of taking them from a cache")
     ap.add_argument("--serve-pool", type=int, default=32, help="served: distinct jobs (operand sets) in the pool")
     ap.add_argument("--serve-requests", type=int, default=240, help="served: requests per load level")
     ap.add_argument("--serve-slots", type=int, default=2, help="served: concurrent batches (streams)")
