@@ -89,6 +89,24 @@ def test_batch_forced_long_rows(reap):
         _check_all(pairs, res, np.float64, "all long")
 
 
+@pytest.mark.parametrize("slots", [512, 1024])
+def test_batch_hash_rows(reap, slots):
+    """Every row the bitmap would take goes to the wavefront hash class instead
+    (512- and 1024-slot tables, argument tables of a batch), plus a product
+    whose rows of 400 products need the larger table."""
+    pairs = _mixed_products(np.float64)
+    pairs.append((synth.uniform_rows(200, 20000, 20, seed=13), synth.uniform_rows(20000, 40000, 20, seed=14)))
+    say("batch hash rows", slots)
+    dA, dB = _device(reap, pairs, torch.float64)
+    with reap.Batch(torch.float64, wave_max_span=-1, wave_hash_slots=slots) as b:
+        b.symbolic(dA, dB)
+        res = b.numeric(dA, dB)
+        b.synchronize()
+        st = b.plan.bin_stats()
+        assert st["wave_bitmap"] == 0 and st["wave_hash"] > 0, st
+        _check_all(pairs, res, np.float64, "hash %d" % slots)
+
+
 def test_batch_of_one_matches_single(reap):
     E = synth.erdos_renyi(900, 900, 0.03, seed=11)
     say("batch of one vs single call")
